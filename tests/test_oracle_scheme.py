@@ -1,0 +1,301 @@
+"""Pins of the oracle's space-time scheme (Sec. 3.1) and lattice step (no GPU).
+
+The checks are properties the method fixes: the minmod limiter equals the
+ratio form of Sec. 3.1, mirror symmetry, exact upwind shifts at Courant
+number 1, no new extrema (TVD), Lax-Wendroff where the limiter is inactive,
+exact mass/momentum bookkeeping on periodic lattices, x-uniform states that
+stay x-uniform bit for bit, zero normal mass flux at diffuse walls, and
+equilibrium fixed points.
+"""
+import math
+
+import numpy as np
+import pytest
+
+
+def _minmod(a, b):
+    return np.where(a * b > 0, np.where(np.abs(a) < np.abs(b), a, b), 0.0)
+
+
+def test_limiter_is_minmod(oracle):
+    # Delta+ * Psi(Delta-/Delta+) with Psi = max(0, min(1, Theta)) equals
+    # minmod(Delta-, Delta+) up to the rounding of the ratio
+    rng = np.random.default_rng(1)
+    vals = np.concatenate([rng.normal(size=400), [0.0, 1.0, -1.0]])
+    for nu in (0.3, 0.9):
+        c = 0.5 * (1 - nu)
+        for k in range(0, len(vals) - 3):
+            fm1, f0, fp1, fp2 = vals[k:k + 4]
+            got = oracle.face_value(nu, fm1, f0, fp1, fp2)
+            ref = f0 + c * float(_minmod(f0 - fm1, fp1 - f0))
+            assert abs(got - ref) <= 4e-16 * max(1.0, abs(ref))
+
+
+def test_face_value_mirror_symmetry(oracle):
+    rng = np.random.default_rng(2)
+    for _ in range(300):
+        a, b, c, d = rng.normal(size=4)
+        nu = rng.uniform(0.05, 1.0)
+        assert oracle.face_value(-nu, a, b, c, d) == oracle.face_value(nu, d, c, b, a)
+
+
+def test_face_value_special_cases(oracle):
+    # constant data: the face carries the constant; |nu| = 1: the upwind value
+    assert oracle.face_value(0.4, 2.5, 2.5, 2.5, 2.5) == 2.5
+    assert oracle.face_value(-0.4, 2.5, 2.5, 2.5, 2.5) == 2.5
+    assert oracle.face_value(1.0, 0.1, 0.7, 0.3, 0.9) == 0.7
+    assert oracle.face_value(-1.0, 0.1, 0.7, 0.3, 0.9) == 0.3
+    # Theta <= 0 (local extremum): first-order upwind
+    assert oracle.face_value(0.5, 1.0, 2.0, 1.5, 0.0) == 2.0
+    # Theta >= 1 (the limiter is inactive): Lax-Wendroff face value
+    nu = 0.3
+    assert abs(oracle.face_value(nu, 4.0, 2.0, 1.0, 0.5) - (2.0 + 0.5 * (1 - nu) * (1.0 - 2.0))) < 1e-15
+
+
+def _lattice(oracle, nx, ny, **kw):
+    return oracle.Lattice(nx, ny, **kw)
+
+
+def test_x_uniform_state_stays_x_uniform_bitwise(oracle):
+    # coupled D2Q9/D2Q36 (Hermite interface), moving walls, body force,
+    # non-uniform initial rho(y), u(y): D_x vanishes exactly for x-uniform data
+    L = _lattice(oracle, 6, 40, kn=0.05, n_low=3, n_high=6, eq_low=2, eq_high=4,
+                 u_wall=((-0.03, 0.0), (0.04, 0.0)), gx=1e-4)
+    L.set_regions(7, 9)
+    y = np.arange(41)[:, None] * np.ones((1, 6))
+    L.init_equilibrium(1.0 + 0.01 * np.sin(y / 7.0), 0.02 * np.cos(y / 5.0), 0.0 * y)
+    L.step(40)
+    for s in (0, 1):
+        f = L.get_populations(s)
+        reg = L.region()
+        for j in range(41):
+            if (reg[j, 0] == 1) == (s == 1):
+                assert np.all(f[:, j, :] == f[:, j, :1]), (s, j)
+
+
+@pytest.mark.parametrize("n,N", [(3, 2), (4, 3), (6, 4)])
+def test_periodic_conservation(oracle, n, N):
+    # fully periodic, one set: total mass is conserved to round-off; total
+    # x-momentum grows by dt * gx * total mass per step (Eq. lbgk, Sec. 3.1).
+    # 2D-varying data, per-axis Courant number 0.3 (the unsplit update is
+    # unstable for diagonal velocities above ~0.37 when data vary in x and y)
+    nx, ny = 12, 11
+    gx = 1e-4
+    x, _ = oracle.gh_rule(n)
+    L = _lattice(oracle, nx, ny, kn=0.2, n_low=n, n_high=n, eq_low=N, gx=gx,
+                 ybc=oracle.YBC_PERIODIC, dt=0.3 / x.max())
+    rng = np.random.default_rng(5)
+    yy, xx = np.mgrid[0:ny + 1, 0:nx]
+    ph = rng.uniform(0, 2 * np.pi, 3)
+    rho = 1 + 0.03 * np.sin(2 * np.pi * xx / nx + ph[0]) * np.cos(2 * np.pi * yy / (ny + 1))
+    ux = 0.05 * np.sin(2 * np.pi * yy / (ny + 1) + ph[1])
+    uy = 0.04 * np.cos(2 * np.pi * xx / nx + ph[2])
+    L.init_equilibrium(rho, ux, uy)
+    c0 = L.conservation()
+    f0 = L.get_populations(0).sum()
+    L.step(300)
+    c1 = L.conservation()
+    assert np.all(np.isfinite(c1))
+    assert abs(L.get_populations(0).sum() - f0) / f0 < 1e-14
+    assert abs(c1[0] - c0[0]) / c0[0] < 1e-13
+    assert abs((c1[1] - c0[1]) - 300 * L.dt * gx * c0[0]) < 1e-12
+    assert abs(c1[2] - c0[2]) < 1e-12
+
+
+def test_unsplit_update_2d_courant_limit(oracle):
+    # pure advection (no collision) of 2D-varying data: the unsplit update of
+    # Sec. 3.1 stays bounded at per-axis Courant 0.3 but not at 0.45
+    n = 16
+    cx, cy, w = oracle.vset(3)
+    yy, xx = np.mgrid[0:n, 0:n]
+    f0 = np.array([w[a] * (1 + 0.1 * np.sin(2 * np.pi * xx / n) * np.sin(2 * np.pi * yy / n))
+                   for a in range(9)])
+    amp = {}
+    for cfl in (0.3, 0.45):
+        L = _lattice(oracle, n, n - 1, kn=1e30, n_low=3, n_high=3, eq_low=2,
+                     dt=cfl / math.sqrt(3), ybc=oracle.YBC_PERIODIC)
+        L.set_populations(0, f0)
+        L.step(600)
+        f = L.get_populations(0)
+        amp[cfl] = np.nanmax(np.abs(f - w[:, None, None]) / w[:, None, None])
+    assert amp[0.3] <= 0.1 + 1e-12
+    assert not (amp[0.45] < 1.0)
+
+
+@pytest.mark.parametrize("n", [3, 4, 6])
+def test_unit_courant_number_is_an_exact_shift(oracle, n):
+    # no collision (Kn huge), dt = 1/xi_max: the fastest axis-aligned
+    # population is shifted by exactly one node per step (F_{i+1/2} = f_i)
+    x, _ = oracle.gh_rule(n)
+    xm = float(np.max(x))
+    L = _lattice(oracle, 9, 6, kn=1e30, n_low=n, n_high=n, eq_low=2, dt=1.0 / xm,
+                 ybc=oracle.YBC_PERIODIC)
+    rng = np.random.default_rng(n)
+    Q = n * n
+    f0 = rng.uniform(0.5, 1.5, (Q, 7, 9))
+    L.set_populations(0, f0)
+    L.set_populations(1, f0)
+    L.step(1)
+    f1 = L.get_populations(0)
+    cx, cy, _ = oracle.vset(n)
+    # abscissa (xm, 0) exists only for odd n; use (xm, y) with y = x_min in
+    # magnitude otherwise: then the y-sweep is not a shift.  Check the pure
+    # x-shift on populations with cy == 0, and the pure y-shift likewise.
+    checked = 0
+    for a in range(Q):
+        if cy[a] == 0.0 and abs(cx[a]) == xm:
+            sh = 1 if cx[a] > 0 else -1
+            np.testing.assert_allclose(f1[a], np.roll(f0[a], sh, axis=1), rtol=0, atol=1e-15)
+            checked += 1
+        if cx[a] == 0.0 and abs(cy[a]) == xm:
+            sh = 1 if cy[a] > 0 else -1
+            np.testing.assert_allclose(f1[a], np.roll(f0[a], sh, axis=0), rtol=0, atol=1e-15)
+            checked += 1
+    if n % 2 == 1:
+        assert checked == 4
+    else:
+        # even n has no zero abscissa: y-uniform data makes the y-flux vanish
+        f0 = np.repeat(rng.uniform(0.5, 1.5, (Q, 1, 9)), 7, axis=1)
+        L.set_populations(0, f0)
+        L.step(1)
+        f1 = L.get_populations(0)
+        for a in range(Q):
+            if abs(cx[a]) == xm:
+                sh = 1 if cx[a] > 0 else -1
+                nuy = cy[a] / xm
+                np.testing.assert_allclose(f1[a], np.roll(f0[a], sh, axis=1), rtol=0, atol=1e-15)
+
+
+def test_tvd_no_new_extrema(oracle):
+    # pure x-advection (y-uniform data, no collision): the limited scheme
+    # creates no new extrema for 0 < |nu| <= 1
+    L = _lattice(oracle, 40, 4, kn=1e30, n_low=3, n_high=3, eq_low=2,
+                 dt=0.9 / math.sqrt(3), ybc=oracle.YBC_PERIODIC)
+    rng = np.random.default_rng(9)
+    row = np.where(np.arange(40) % 13 < 6, 1.0, 0.2) + 0.1 * rng.uniform(size=40)
+    f0 = np.tile(row, (9, 5, 1))
+    L.set_populations(0, f0)
+    cx, cy, _ = oracle.vset(3)
+    for _ in range(30):
+        L.step(1)
+        f = L.get_populations(0)
+        for a in range(9):
+            if cy[a] == 0:
+                assert f[a].max() <= row.max() + 1e-15 and f[a].min() >= row.min() - 1e-15
+
+
+def test_lax_wendroff_where_limiter_inactive(oracle):
+    # decaying data (Theta >= 1 everywhere away from the periodic seam):
+    # interior update equals Lax-Wendroff f - nu/2 (f+ - f-) + nu^2/2 (f+ - 2f + f-)
+    nx = 30
+    dt = 0.6 / math.sqrt(3)
+    L = _lattice(oracle, nx, 4, kn=1e30, n_low=3, n_high=3, eq_low=2, dt=dt,
+                 ybc=oracle.YBC_PERIODIC)
+    row = np.exp(-0.2 * np.arange(nx))
+    f0 = np.tile(row, (9, 5, 1))
+    L.set_populations(0, f0)
+    L.step(1)
+    f1 = L.get_populations(0)
+    cx, cy, _ = oracle.vset(3)
+    a = [k for k in range(9) if cx[k] > 0 and cy[k] == 0][0]
+    nu = cx[a] * dt
+    i = np.arange(3, nx - 3)
+    lw = row[i] - 0.5 * nu * (row[i + 1] - row[i - 1]) + 0.5 * nu * nu * (row[i + 1] - 2 * row[i] + row[i - 1])
+    np.testing.assert_allclose(f1[a, 2, i], lw, rtol=1e-13)
+
+
+@pytest.mark.parametrize("n,N", [(3, 2), (4, 3), (6, 4)])
+def test_diffuse_wall_zero_normal_mass_flux(oracle, n, N):
+    # after the wall treatment (Sec. 3.2) the wall node carries no net mass
+    # through the wall: sum xi_y f = 0
+    L = _lattice(oracle, 5, 20, kn=0.1, n_low=n, n_high=n, eq_low=N,
+                 u_wall=((0.05, 0.0), (-0.02, 0.0)))
+    rng = np.random.default_rng(3)
+    L.init_equilibrium(1 + 0.02 * rng.uniform(-1, 1, (21, 5)), 0.03 * rng.uniform(-1, 1, (21, 5)),
+                       0.02 * rng.uniform(-1, 1, (21, 5)))
+    L.step(3)
+    f = L.get_populations(0)
+    cx, cy, w = oracle.vset(n)
+    for j in (0, 20):
+        flux = np.einsum("a,ai->i", cy, f[:, j, :])
+        assert np.max(np.abs(flux)) < 1e-15
+
+
+@pytest.mark.parametrize("n,N", [(3, 2), (4, 3), (6, 4)])
+def test_wall_equilibrium_is_fixed_point(oracle, n, N):
+    # a uniform equilibrium moving with both walls (tangentially) is steady
+    uw = 0.04
+    L = _lattice(oracle, 4, 12, kn=0.1, n_low=n, n_high=n, eq_low=N,
+                 u_wall=((uw, 0.0), (uw, 0.0)))
+    L.init_equilibrium(1.0, uw, 0.0)
+    f0 = L.get_populations(0)
+    L.step(5)
+    np.testing.assert_allclose(L.get_populations(0), f0, rtol=0, atol=2e-16)
+
+
+def test_paper_interface_preserves_uniform_equilibrium(oracle):
+    # interpolation/extrapolation interface (Sec. 2.2): a uniform equilibrium
+    # is rebuilt exactly at the interface rows; the whole state is steady
+    L = _lattice(oracle, 4, 30, kn=0.1, n_low=3, n_high=6, eq_low=2, eq_high=2,
+                 iface=oracle.IFACE_PAPER, u_wall=((0.03, 0.0), (0.03, 0.0)))
+    L.set_regions(6, 8)
+    L.init_equilibrium(1.0, 0.03, 0.0)
+    r0 = L.moments()
+    L.step(10)
+    r1 = L.moments()
+    for a, b in zip(r0, r1):
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-15)
+    reg = L.region()
+    assert reg[6, 0] == 2 and reg[30 - 8, 0] == 2
+
+
+def test_paper_interface_rows(oracle):
+    # interface row = equilibrium at the averaged (rho, u) + same-side
+    # non-equilibrium part, in both sets
+    L = _lattice(oracle, 4, 30, kn=0.1, n_low=3, n_high=6, eq_low=2, eq_high=2,
+                 iface=oracle.IFACE_PAPER, u_wall=((-0.05, 0.0), (0.05, 0.0)))
+    L.set_regions(6, 8)
+    L.init_equilibrium()
+    L.step(25)
+    fl, fh = L.get_populations(0), L.get_populations(1)
+    I, l, h = 6, 7, 5
+    rl, uxl, uyl = oracle.moments(3, fl[:, l, 0])
+    rh, uxh, uyh = oracle.moments(6, fh[:, h, 0])
+    rI, uxI, uyI = 0.5 * (rl + rh), 0.5 * (uxl + uxh), 0.5 * (uyl + uyh)
+    want_l = oracle.equilibrium(3, 2, rI, uxI, uyI) + fl[:, l, 0] - oracle.equilibrium(3, 2, rl, uxl, uyl)
+    want_h = oracle.equilibrium(6, 2, rI, uxI, uyI) + fh[:, h, 0] - oracle.equilibrium(6, 2, rh, uxh, uyh)
+    np.testing.assert_allclose(fl[:, I, 0], want_l, atol=1e-16)
+    np.testing.assert_allclose(fh[:, I, 0], want_h, atol=1e-16)
+
+
+def test_coupled_equals_uniform_when_sets_coincide(oracle):
+    # Hermite interface between two copies of the same set: identical to the
+    # single-set run, bit for bit
+    kw = dict(kn=0.1, n_low=4, n_high=4, eq_low=3, eq_high=3, u_wall=((-0.05, 0.0), (0.05, 0.0)),
+              gx=1e-5)
+    A = _lattice(oracle, 4, 24, **kw)
+    B = _lattice(oracle, 4, 24, **kw)
+    B.set_regions(5, 7)
+    A.init_equilibrium()
+    B.init_equilibrium()
+    A.step(60)
+    B.step(60)
+    for a, b in zip(A.moments(), B.moments()):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_region_change_round_trip(oracle):
+    # lifting band rows to the high set and restricting them back returns the
+    # low-order populations (exact low-order round trip through the projection)
+    L = _lattice(oracle, 4, 24, kn=0.1, n_low=3, n_high=6, eq_low=2, eq_high=4,
+                 u_wall=((-0.05, 0.0), (0.05, 0.0)))
+    L.set_regions(4, 4)
+    L.init_equilibrium()
+    L.step(50)
+    f0 = L.get_populations(0)
+    L.update_regions(9, 9)
+    L.update_regions(4, 4)
+    f1 = L.get_populations(0)
+    reg = L.region()
+    m = reg == 0
+    np.testing.assert_allclose(f1[:, m], f0[:, m], rtol=0, atol=1e-15)
