@@ -1,0 +1,187 @@
+/*
+ * lb.h -- C ABI of the MI355X multiscale lattice Boltzmann library.
+ *
+ * The library advances the discrete-velocity BGK equation (Meng, Zhang &
+ * Shan, "Multiscale lattice Boltzmann approach to modeling gas flows",
+ * Sec. 2.1, Eq. (lbgk)) on a 2D lattice with the forward-Euler / TVD-minmod
+ * scheme of Sec. 3.1, diffuse-reflection walls (Sec. 3.2), a low-order
+ * Gauss-Hermite velocity set in the core and a high-order set in bands next
+ * to the walls, joined by an interface step (Sec. 2.2).
+ *
+ * Conventions
+ *  - Every call returns an lb_status (LB_OK = 0, errors < 0); nothing throws
+ *    or aborts across the ABI.  lb_last_error() returns a thread-local text
+ *    for the last failure.
+ *  - Units: grid spacing 1; velocities in units of sqrt(R T0), so the
+ *    Gauss-Hermite abscissae are the particle speeds; T = 1.  Node rows are
+ *    j = 0..ny (ny + 1 rows); with walls, rows 0 and ny are the wall nodes and
+ *    the channel height ny is the length of Eq. (KN): the relaxation time at
+ *    density rho_ref is kn * ny.
+ *  - A velocity set is named by its 1D point count n: 3 = D2Q9, 4 = D2Q16,
+ *    6 = D2Q36 (tensor products of the n-point Gauss-Hermite rule, Sec. 2.1).
+ *    Population alpha = p + n*q has velocity (x_p, x_q), abscissae ascending.
+ *  - Host arrays of lattice fields are [ny+1][nx] doubles, row j slow.
+ *    Population arrays are [Q][ny+1][nx] doubles.
+ *  - Memory: the caller owns one device workspace (size from
+ *    lb_workspace_bytes) and a HIP stream; the library never allocates device
+ *    memory.  Host pointers are only read or written during the call.
+ *  - Asynchrony: lb_step and the on-device variants enqueue work on the
+ *    stream and return; errors found by kernels surface at the next call that
+ *    synchronises (lb_conservation, host-side moments, get_* calls).
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,        /* invalid argument or parameter combination */
+    LB_ENOMEM = -2,        /* workspace too small */
+    LB_EDEVICE = -3,       /* a HIP runtime call failed */
+    LB_EUNSTABLE = -4,     /* a reduction found a non-finite value */
+    LB_EUNSUPPORTED = -5,  /* valid, but no kernel was built for it */
+    LB_ESTATE = -6         /* call out of order (e.g. step before init) */
+} lb_status;
+
+typedef enum { LB_STORE_F64 = 0, LB_STORE_F32 = 1, LB_STORE_BF16 = 2 } lb_storage;
+typedef enum { LB_IFACE_HERMITE = 0, LB_IFACE_PAPER = 1 } lb_iface;
+typedef enum { LB_TAU_CONST = 0, LB_TAU_RHO = 1 } lb_tau_mode;
+typedef enum { LB_XBC_PERIODIC = 0, LB_XBC_PRESSURE = 1 } lb_xbc;
+typedef enum { LB_YBC_WALLS = 0, LB_YBC_PERIODIC = 1 } lb_ybc;
+
+typedef struct lb_params {
+    int32_t nx, ny;            /* nx columns (>= 2); ny intervals -> ny+1 rows (>= 4) */
+    int32_t n_low, n_high;     /* 1D Gauss-Hermite points of the low / high set */
+    int32_t eq_low, eq_high;   /* Hermite order of each set's equilibrium, Eq. (approxfeq) */
+    int32_t force_low, force_high; /* order of the body-force expansion; 0 = eq order */
+    int32_t tau_mode;          /* lb_tau_mode: constant, or kn*ny*rho_ref/rho */
+    int32_t xbc, ybc;          /* lb_xbc, lb_ybc */
+    int32_t iface;             /* lb_iface */
+    int32_t storage;           /* lb_storage of the populations */
+    int32_t tile_w;            /* columns per band tile; 0 = nx (one tile) */
+    double kn;                 /* Knudsen number of Eq. (KN) at rho_ref */
+    double rho_ref;            /* reference density (also the storage shift) */
+    double cfl;                /* per-axis Courant number of the fastest abscissa */
+    double dt;                 /* > 0 overrides cfl: explicit time step */
+    double gx, gy;             /* body force per unit mass */
+    double u_wall[4];          /* bottom (x, y), top (x, y) wall velocity */
+    double rho_in, rho_out;    /* pressure x-boundary densities (LB_XBC_PRESSURE) */
+} lb_params;
+
+typedef struct lb_lattice lb_lattice;
+
+/* Text of the last error on this thread ("" if none). */
+const char *lb_last_error(void);
+
+/* Fill p with defaults: D2Q9 everywhere, eq order 2, HERMITE interface,
+ * F64 storage, walls, periodic x, kn = 0.1, rho_ref = 1, cfl = 0.5. */
+lb_status lb_params_default(lb_params *p);
+
+/* Device workspace needed for a lattice with parameters p (0 on invalid p). */
+size_t lb_workspace_bytes(const lb_params *p);
+
+/* Create a lattice in the caller's device workspace (>= lb_workspace_bytes,
+ * 256-byte aligned), enqueuing on hip_stream (a hipStream_t; NULL = the null
+ * stream).  Validates p (LB_EINVAL: sizes, orders above floor(n - 1/2)
+ * (the quadrature-degree rule after Eq. (approxfeq)), Courant number above
+ * 0.5, dt above the relaxation time; LB_EUNSUPPORTED: set pairs without a
+ * kernel).  Regions start as all-low; populations are unset until
+ * lb_init_equilibrium or lb_set_populations. */
+lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t bytes,
+                            void *hip_stream, lb_lattice **out);
+
+void lb_destroy_lattice(lb_lattice *L);
+
+/* Time step, relaxation time at rho_ref and number of band tiles. */
+lb_status lb_get_info(const lb_lattice *L, double *dt, double *tau0, int32_t *ntiles);
+
+/* Domain decomposition (Sec. 2.2 procedure): per band tile t, rows
+ * j < band_lo[t] and j > ny - band_hi[t] use the high set, the rest the low
+ * set.  With LB_IFACE_PAPER, the first row past each non-empty band is the
+ * interface row of Sec. 2.2 (not evolved), and all tiles must have the same
+ * bands.  Host arrays of ntiles entries.  Existing populations are not
+ * converted: use lb_update_regions for that. */
+lb_status lb_set_regions(lb_lattice *L, const int32_t *band_lo, const int32_t *band_hi);
+lb_status lb_get_regions(const lb_lattice *L, int32_t *band_lo, int32_t *band_hi);
+
+/* Equilibrium start (Eq. approxfeq) from host fields; NULL = rho_ref / 0. */
+lb_status lb_init_equilibrium(lb_lattice *L, const double *rho, const double *ux, const double *uy);
+
+/* Advance nsteps time steps (Sec. 3.1 update, Sec. 3.2 walls, Sec. 2.2
+ * interface).  Asynchronous on the lattice stream. */
+lb_status lb_step(lb_lattice *L, int64_t nsteps);
+
+/* Density and velocity of every node ([ny+1][nx], FP64; interface rows report
+ * the interpolated values).  on_device != 0: the three pointers are device
+ * memory and the call is asynchronous; else host memory and the call waits. */
+lb_status lb_moments(lb_lattice *L, double *rho, double *ux, double *uy, int32_t on_device);
+
+/* out[0..2] = sum rho, sum rho ux, sum rho uy over all nodes, reduced in FP64
+ * in a fixed order (deterministic).  Waits.  LB_EUNSTABLE if not finite. */
+lb_status lb_conservation(lb_lattice *L, double out[3]);
+
+/* Populations of set which (0 = low, 1 = high) as FP64 host arrays
+ * [Q][ny+1][nx].  get: nodes not evolved in that set (and not interface
+ * rows) read as NaN.  set: only those nodes are read; the ghost, image and
+ * interface entries are then rebuilt. */
+lb_status lb_get_populations(lb_lattice *L, int32_t which, double *host);
+lb_status lb_set_populations(lb_lattice *L, int32_t which, const double *host);
+
+/* Raw state (both sets' population buffers + step counter) for
+ * checkpointing; bit-exact round trip.  Waits. */
+size_t lb_state_bytes(const lb_lattice *L);
+lb_status lb_get_state(lb_lattice *L, void *host, size_t bytes);
+lb_status lb_set_state(lb_lattice *L, const void *host, size_t bytes);
+int64_t lb_step_count(const lb_lattice *L);
+
+/* Non-equilibrium indicator per node (an isothermal form of the 'B'
+ * breakdown parameter of Sec. 2.2: max over the second-order Hermite
+ * components of |a_km - rho ux^k uy^m| / rho), FP64 [ny+1][nx]. */
+lb_status lb_indicator(lb_lattice *L, double *B, int32_t on_device);
+
+/* Re-decompose from the indicator: per tile, the bottom band reaches one row
+ * past the highest lower-half row with B > theta (mirrored at the top),
+ * clamped to [bmin, bmax].  Nodes that change set are converted by the
+ * Hermite projection.  Waits (the band arrays come back to the host). */
+lb_status lb_update_regions(lb_lattice *L, double theta, int32_t bmin, int32_t bmax);
+
+/* Replace the decomposition with explicit bands, converting switched nodes
+ * by the Hermite projection (lift to / restriction from the high set). */
+lb_status lb_change_regions(lb_lattice *L, const int32_t *band_lo, const int32_t *band_hi);
+
+/* Hermite-moment projection of n nodes from set (ns, eqs) to set (nd, eqd)
+ * (Sec. 2.2 in moment form): equilibrium rebuilt in the target set from
+ * rho, u; non-equilibrium coefficients carried where both sets resolve
+ * them; missing ones from closure[nd*nd per node] (NULL = 0).  Device
+ * arrays [node][Q] in FP64.  Asynchronous on hip_stream. */
+lb_status lb_project(int32_t ns, int32_t eqs, int32_t nd, int32_t eqd, const double *f_src,
+                     const double *closure, double *f_dst, int64_t n, void *hip_stream);
+
+/* Kernel timing: when enabled, every update-kernel launch is bracketed by
+ * HIP events on the lattice stream; lb_kernel_times returns, for the
+ * dominant update kernel (the set that moves the most bytes per step) and
+ * for all update kernels, the summed duration in ms and the launch count,
+ * then clears them.  Waits. */
+lb_status lb_set_timing(lb_lattice *L, int32_t enable);
+lb_status lb_kernel_times(lb_lattice *L, double *ms_high, int64_t *n_high, double *ms_all,
+                          int64_t *n_all);
+
+/* Rows per work item of the update kernels (tuning; 0 = automatic: enough
+ * items to fill the GPU, at most 16 rows). */
+lb_status lb_set_strip_rows(lb_lattice *L, int32_t rows);
+
+/* Number of nodes in each region: [0] low set, [1] high set, [2] interface
+ * rows (interpolation mode only). */
+lb_status lb_region_counts(const lb_lattice *L, int64_t counts[3]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

@@ -1,0 +1,71 @@
+// lb_inst.hpp -- instantiation helpers for one storage type.
+#pragma once
+#include "lb_kernels.hpp"
+#include "lb_registry.hpp"
+
+namespace lbk {
+
+template <class ST, class S, class O>
+struct Inst {
+    static int nodes_grid(const NodeArgs &a) { return (a.g.nrow * a.g.nx + 255) / 256; }
+    static void update(const StepArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_update<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
+    }
+    static void finish(const StepArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_finish<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
+    }
+    static void refresh(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_refresh<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void init_eq(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_init_eq<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void set_pop(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_set_pop<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void get_pop(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_get_pop<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void moments(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_moments<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void indicator(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_indicator<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void convert(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_convert<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
+    }
+    static void paper_iface(const NodeArgs &a, int copy, int recompute, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_paper_iface<ST, S, O>), dim3(grid), dim3(256), 0, s, a, copy, recompute);
+    }
+    static void project(const double *fs, const double *cl, double *fd, int64_t n, hipStream_t s) {
+        int grid = int((n + 127) / 128);
+        if (grid > 0) hipLaunchKernelGGL((k_project<S, O>), dim3(grid), dim3(128), 0, s, fs, cl, fd, n);
+    }
+    static KernelSet make(int storage) {
+        KernelSet k{};
+        k.storage = storage;
+        k.nS = S::N;
+        k.eqS = S::EQ;
+        k.nO = O::N;
+        k.eqO = O::EQ;
+        k.update = &update;
+        k.finish = &finish;
+        k.refresh = &refresh;
+        k.init_eq = &init_eq;
+        k.set_pop = &set_pop;
+        k.get_pop = &get_pop;
+        k.moments = &moments;
+        k.indicator = &indicator;
+        k.convert = &convert;
+        k.paper_iface = &paper_iface;
+        k.project = &project;
+        k.update_kernel = reinterpret_cast<const void *>(&k_update<ST, S, O>);
+        return k;
+    }
+};
+
+}  // namespace lbk
+
+#define LB_PAIR(ST, SID, n1, e1, n2, e2) \
+    lbk::Inst<ST, lbt::VSet<n1, e1>, lbt::VSet<n2, e2>>::make(SID)

@@ -1,0 +1,84 @@
+// lb_internal.hpp -- argument blocks shared by the host runtime and kernels.
+//
+// HBM layout of one velocity set: Q planes, one per population, each holding
+// rows -2..ny+2 (two ghost rows beyond each wall) of `pitch` elements.
+// Column c of row j of plane a lives at element
+//     a * plane + rowbase + (j + 2) * pitch + c,      c in [-2, nx + 2)
+// so the two left ghost columns of a row sit in the padding at the end of
+// the previous row.  rowbase and pitch are multiples of 128 bytes, so every
+// 64-column wave load of a row starts on a cache-line boundary.  Each set is
+// allocated over the whole lattice; only the rows evolved in that set (plus
+// two halo rows) are ever touched, so the extra capacity costs no traffic.
+// Two copies (ping-pong) per set.
+#pragma once
+#include <stdint.h>
+
+namespace lbi {
+
+enum : int32_t { XBC_PERIODIC = 0, XBC_PRESSURE = 1 };
+enum : int32_t { YBC_WALLS = 0, YBC_PERIODIC = 1 };
+enum : int32_t { IF_HERMITE = 0, IF_PAPER = 1 };
+enum : int32_t { TAU_CONST = 0, TAU_RHO = 1 };
+enum : int32_t { REG_LOW = 0, REG_HIGH = 1, REG_IFACE = 2 };
+
+struct Buf {
+    char *base[2];     // ping-pong copies
+    int64_t plane;     // elements per population plane
+    int32_t pitch;     // elements per row
+    int32_t rowbase;   // element offset of (row -2, column 0) in a plane
+};
+
+struct Geo {
+    int32_t nx, ny, nrow, tile_w, ntiles, xbc, ybc, iface;
+    const int32_t *blo;   // device: high rows at the bottom wall, per tile
+    const int32_t *bhi;   // device: high rows at the top wall, per tile
+};
+
+struct Phys {
+    double dt;         // time step
+    double omega0;     // dt / tau at rho_ref
+    double rho_ref;
+    double rho_in, rho_out;
+    double gx, gy;
+    double uw[4];      // bottom x, y, top x, y
+    int32_t tau_mode;
+    int32_t pad;
+};
+
+// Per-set kernel constants, in double and float: nu_p = x_p dt and
+// k_p = |nu_p| (1 - |nu_p|) / 2 for the p-th 1D abscissa.
+struct SetK {
+    double nu[8], kk[8];
+    float nuf[8], kkf[8];
+};
+
+struct StepArgs {
+    Geo g;
+    Phys ph;
+    Buf self, other;     // the set this kernel evolves, and its partner
+    SetK ks;             // constants of `self`
+    double rho_shift;    // storage shift (rho_ref for F32/BF16, 0 for F64)
+    int32_t cur;         // source copy; the kernel writes copy cur ^ 1
+    int32_t self_high;   // 1 if `self` is the high set
+    int32_t nitems;      // work items (64 columns x a strip of rows)
+    int32_t chunk;       // items per XCD slot (XCD-aware block mapping)
+    const int32_t *items;   // device: 4 ints per item: i0, j0, j1, unused
+};
+
+// Arguments of the non-step kernels (one thread per node).
+struct NodeArgs {
+    Geo g;
+    Phys ph;
+    Buf self, other;
+    double rho_shift;
+    int32_t cur;
+    int32_t self_high;
+    int32_t which;       // set index of `self` in the caller's numbering
+    int32_t pad;
+    const double *in0, *in1, *in2;   // device FP64 inputs (fields or populations)
+    double *out0, *out1, *out2;      // device FP64 outputs
+    const int32_t *oblo, *obhi;      // previous bands (region change)
+    const double *closure;           // optional closure coefficients (lift)
+};
+
+}  // namespace lbi

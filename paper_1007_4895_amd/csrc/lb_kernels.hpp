@@ -1,0 +1,859 @@
+// lb_kernels.hpp -- HIP kernels for gfx950 (CDNA4, wave64).
+//
+// The hot kernel, k_update, advances every node of one velocity set by one
+// time step of Sec. 3.1:
+//   f^{n+1} = f - nu_x [F_{i+1/2} - F_{i-1/2}] - nu_y [F_{j+1/2} - F_{j-1/2}]
+//             + (dt / tau)(f_eq - f) + dt g,
+// with the TVD/minmod face values of Sec. 3.1, the order-N Hermite
+// equilibrium of Eq. (approxfeq) and the Hermite body force (Sec. 2.1).
+//
+// Mapping: one wave = 64 consecutive columns x a strip of rows.  Each lane
+// owns one column and marches up the strip keeping, per population, the
+// values and limited slopes it needs along y in registers, so every
+// population value is loaded from HBM once per step.  The x neighbours come
+// from the neighbouring lanes through DPP wave shifts; the two columns
+// beyond each side of the wave come from one 4-lane halo load.  The minmod
+// limited slope Delta+ Psi(Delta-/Delta+) is evaluated as med3(Delta-,
+// Delta+, 0), which is the same function.
+//
+// Nodes with extra duties -- wall rows (diffuse reflection, Sec. 3.2),
+// ghost and row images, pressure columns, nodes that a stencil of the
+// partner set reads (Hermite projection, Sec. 2.2 in moment form) -- are
+// finished by k_finish, a node-local FP64 pass over a list of those nodes,
+// so that the hot kernel carries none of that register footprint.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lb_internal.hpp"
+#include "lb_tables.hpp"
+
+namespace lbk {
+
+using namespace lbi;
+using lbt::NoSet;
+using lbt::VSet;
+
+// ------------------------------------------------------------------ storage
+struct StF64 {
+    using S = double;
+    using M = double;
+    static constexpr int bytes = 8;
+    __device__ static __forceinline__ M ld(const S *p) { return *p; }
+    __device__ static __forceinline__ void st(S *p, M v) { *p = v; }
+    __device__ static __forceinline__ double ldd(const S *p) { return *p; }
+    __device__ static __forceinline__ void std_(S *p, double v) { *p = v; }
+    __device__ static __forceinline__ M bld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    __device__ static __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, M v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
+                                              r, vo, so, 0);
+    }
+};
+
+struct StF32 {
+    using S = float;
+    using M = float;
+    static constexpr int bytes = 4;
+    __device__ static __forceinline__ M ld(const S *p) { return *p; }
+    __device__ static __forceinline__ void st(S *p, M v) { *p = v; }
+    __device__ static __forceinline__ double ldd(const S *p) { return double(*p); }
+    __device__ static __forceinline__ void std_(S *p, double v) { *p = float(v); }
+    __device__ static __forceinline__ M bld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    __device__ static __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, M v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+    }
+};
+
+// bfloat16 bits; round to nearest even on store
+struct StBF16 {
+    using S = uint16_t;
+    using M = float;
+    static constexpr int bytes = 2;
+    __device__ static __forceinline__ float cvt(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+    __device__ static __forceinline__ uint16_t rne(float v) {
+        uint32_t u = __float_as_uint(v);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return uint16_t(u >> 16);
+    }
+    __device__ static __forceinline__ M ld(const S *p) { return cvt(*p); }
+    __device__ static __forceinline__ void st(S *p, M v) { *p = rne(v); }
+    __device__ static __forceinline__ double ldd(const S *p) { return double(cvt(*p)); }
+    __device__ static __forceinline__ void std_(S *p, double v) { *p = rne(float(v)); }
+    __device__ static __forceinline__ M bld(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so) {
+        return cvt(__builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+    }
+    __device__ static __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, M v) {
+        __builtin_amdgcn_raw_buffer_store_b16(rne(v), r, vo, so, 0);
+    }
+};
+
+// ---------------------------------------------------------- lane exchange
+constexpr int DPP_WAVE_SHL1 = 0x130;   // lane l <- lane l+1
+constexpr int DPP_WAVE_SHR1 = 0x138;   // lane l <- lane l-1
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float src, float old) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double src, double old) {
+    long long s = __double_as_longlong(src), o = __double_as_longlong(old);
+    int slo = int(s & 0xffffffffll), shi = int(s >> 32);
+    int olo = int(o & 0xffffffffll), ohi = int(o >> 32);
+    int rlo = __builtin_amdgcn_update_dpp(olo, slo, CTRL, 0xf, 0xf, false);
+    int rhi = __builtin_amdgcn_update_dpp(ohi, shi, CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)((unsigned long long)(unsigned)rlo |
+                                            ((unsigned long long)(unsigned)rhi << 32)));
+}
+
+// minmod(a, b) = median(a, b, 0)
+__device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+__device__ __forceinline__ double minmod(double a, double b) {
+    return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
+}
+
+// ------------------------------------------------------------------ regions
+__device__ __forceinline__ int reg_of(int lo, int hi, int j, const Geo &g) {
+    if (j < lo || j > g.ny - hi) return REG_HIGH;
+    if (g.iface == IF_PAPER && ((lo > 0 && j == lo) || (hi > 0 && j == g.ny - hi))) return REG_IFACE;
+    return REG_LOW;
+}
+__device__ __forceinline__ int tile_of(int i, const Geo &g) { return g.ntiles == 1 ? 0 : i / g.tile_w; }
+__device__ __forceinline__ int region_at(int i, int j, const Geo &g) {
+    int t = tile_of(i, g);
+    return reg_of(g.blo[t], g.bhi[t], j, g);
+}
+
+// Is a cross-neighbour within distance 2 of node (i, j) in region `want`?
+// lo, hi: bands of the tile of column i.
+__device__ bool neighbour_in(int i, int j, int want, int lo, int hi, const Geo &g) {
+#pragma unroll
+    for (int d = -2; d <= 2; ++d) {
+        if (d == 0) continue;
+        int jj = j + d;
+        if (jj < 0 || jj > g.ny) {
+            if (g.ybc != YBC_PERIODIC) continue;
+            jj = (jj + g.nrow) % g.nrow;
+        }
+        if (reg_of(lo, hi, jj, g) == want) return true;
+    }
+    if (g.ntiles > 1) {
+        int r = i % g.tile_w;
+        if (r < 2 || r >= g.tile_w - 2) {
+            int t = i / g.tile_w;
+            for (int d = -2; d <= 2; ++d) {
+                if (d == 0) continue;
+                int ii = i + d;
+                if (ii < 0 || ii >= g.nx) {
+                    if (g.xbc != XBC_PERIODIC) continue;
+                    ii = (ii + g.nx) % g.nx;
+                }
+                if (ii / g.tile_w != t && region_at(ii, j, g) == want) return true;
+            }
+        }
+    }
+    return false;
+}
+
+// ---------------------------------------------------- FP64 node arithmetic
+template <class SS>
+__device__ __forceinline__ double w_of(int a) {
+    using TB = typename SS::T;
+    return TB::rule.w[a % SS::N] * TB::rule.w[a / SS::N];
+}
+
+// rho, u of absolute populations (Eq. an, zeroth and first coefficients)
+template <class SS>
+__device__ void moments_d(const double *f, double &rho, double &ux, double &uy) {
+    using TB = typename SS::T;
+    double r = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+    for (int a = 0; a < SS::Q; ++a) {
+        r += f[a];
+        jx += TB::rule.x[a % SS::N] * f[a];
+        jy += TB::rule.x[a / SS::N] * f[a];
+    }
+    rho = r;
+    ux = jx / r;
+    uy = jy / r;
+}
+
+// Order-EQ Hermite equilibrium (Eq. approxfeq, T = 1), absolute values
+template <class SS>
+__device__ void feq_d(double rho, double ux, double uy, double *out) {
+    using TB = typename SS::T;
+    constexpr int N = SS::N, EQ = SS::EQ;
+    double px[EQ + 1], py[EQ + 1];
+    px[0] = py[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= EQ; ++k) {
+        px[k] = px[k - 1] * ux;
+        py[k] = py[k - 1] * uy;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double B[EQ + 1];
+#pragma unroll
+        for (int k = 0; k <= EQ; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m + k <= EQ; ++m) s += py[m] * TB::hk.v[m][q];
+            B[k] = s * px[k];
+        }
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k <= EQ; ++k) s += TB::hk.v[k][p] * B[k];
+            out[p + N * q] = TB::rule.w[p] * TB::rule.w[q] * rho * s;
+        }
+    }
+}
+
+// Hermite-moment projection from set SS to set DD (FP64):
+// equilibrium rebuilt in DD from rho, u; non-equilibrium coefficients a_km -
+// a_eq,km carried for k, m below both sets' point counts; the rest from the
+// closure (NULL = 0).  A set projected on itself is copied.
+template <class SS, class DD>
+__device__ void project_d(const double *fs, double *fd, const double *closure) {
+    if constexpr (SS::N == DD::N && SS::EQ == DD::EQ) {
+#pragma unroll
+        for (int a = 0; a < SS::Q; ++a) fd[a] = fs[a];
+    } else {
+        using TS = typename SS::T;
+        using TD = typename DD::T;
+        constexpr int NS = SS::N, ND = DD::N;
+        constexpr int NM = NS < ND ? NS : ND;
+        double t[NS][NM];
+#pragma unroll
+        for (int p = 0; p < NS; ++p)
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) s += fs[p + NS * q] * TS::he.v[m][q];
+                t[p][m] = s;
+            }
+        double a[NM][NM];
+#pragma unroll
+        for (int k = 0; k < NM; ++k)
+#pragma unroll
+            for (int m = 0; m < NM; ++m) {
+                double s = 0.0;
+#pragma unroll
+                for (int p = 0; p < NS; ++p) s += TS::he.v[k][p] * t[p][m];
+                a[k][m] = s;
+            }
+        const double rho = a[0][0], ux = a[1][0] / rho, uy = a[0][1] / rho;
+        double px[ND + 1], py[ND + 1];
+        px[0] = py[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k <= ND; ++k) {
+            px[k] = px[k - 1] * ux;
+            py[k] = py[k - 1] * uy;
+        }
+        double c[ND][ND];
+#pragma unroll
+        for (int k = 0; k < ND; ++k)
+#pragma unroll
+            for (int m = 0; m < ND; ++m) {
+                double eqd = (k + m <= DD::EQ) ? rho * px[k] * py[m] : 0.0;
+                double neq;
+                if (k < NM && m < NM) {
+                    double eqs = (k + m <= SS::EQ) ? rho * px[k] * py[m] : 0.0;
+                    neq = a[k][m] - eqs;
+                } else {
+                    neq = closure ? closure[k * ND + m] : 0.0;
+                }
+                c[k][m] = eqd + neq;
+            }
+#pragma unroll
+        for (int q = 0; q < ND; ++q) {
+            double B[ND];
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                double s = 0.0;
+#pragma unroll
+                for (int m = 0; m < ND; ++m) s += c[k][m] * TD::hk.v[m][q];
+                B[k] = s;
+            }
+#pragma unroll
+            for (int p = 0; p < ND; ++p) {
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < ND; ++k) s += TD::hk.v[k][p] * B[k];
+                fd[p + ND * q] = TD::rule.w[p] * TD::rule.w[q] * s;
+            }
+        }
+    }
+}
+
+// Diffuse reflection at a wall node (Sec. 3.2): rho_W from the populations
+// moving into the wall, the populations leaving the wall set to rho_W S,
+// S = f_eq(rho = 1, u_wall); populations with xi_y = 0 untouched.
+template <class SS>
+__device__ void diffuse_wall_d(double *f, bool top, const Phys &ph) {
+    using TB = typename SS::T;
+    double Sw[SS::Q];
+    const double *uw = top ? ph.uw + 2 : ph.uw;
+    feq_d<SS>(1.0, uw[0], uw[1], Sw);
+    const double nsign = top ? -1.0 : 1.0;
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int a = 0; a < SS::Q; ++a) {
+        double cn = TB::rule.x[a / SS::N] * nsign;
+        if (cn < 0.0) num += -cn * f[a];
+        else if (cn > 0.0) den += cn * Sw[a];
+    }
+    const double rw = num / den;
+#pragma unroll
+    for (int a = 0; a < SS::Q; ++a)
+        if (TB::rule.x[a / SS::N] * nsign > 0.0) f[a] = rw * Sw[a];
+}
+
+// ---------------------------------------------------- node stores (FP64 in)
+template <class ST, class SS>
+__device__ __forceinline__ typename ST::S *plane0(const Buf &b, int copy) {
+    return reinterpret_cast<typename ST::S *>(b.base[copy]) + b.rowbase;
+}
+
+template <class ST, class SS>
+__device__ void load_node_d(const Buf &b, int copy, int i, int j, double shift, double *f) {
+    const typename ST::S *p = plane0<ST, SS>(b, copy) + (int64_t)(j + 2) * b.pitch + i;
+#pragma unroll
+    for (int a = 0; a < SS::Q; ++a) f[a] = ST::ldd(p + a * b.plane) + w_of<SS>(a) * shift;
+}
+
+template <class ST, class SS>
+__device__ void store_node_d(const Buf &b, int copy, int i, int j, double shift, const double *f) {
+    typename ST::S *p = plane0<ST, SS>(b, copy) + (int64_t)(j + 2) * b.pitch + i;
+#pragma unroll
+    for (int a = 0; a < SS::Q; ++a) ST::std_(p + a * b.plane, f[a] - w_of<SS>(a) * shift);
+}
+
+// Write node (i, j)'s populations f (set SS, absolute) to (i, j) when
+// `own`, and to every ghost entry that stands for it: the wall ghost rows
+// (Sec. 3.2: copies of the wall node), periodic images, and the pressure
+// boundary columns (equilibrium at the prescribed density with the edge
+// node's velocity plus the edge node's non-equilibrium part).
+template <class ST, class SS>
+__device__ void emit_node(const Buf &b, int copy, int i, int j, double shift, const double *f, bool own,
+                          const Geo &g, const Phys &ph) {
+    if (own) store_node_d<ST, SS>(b, copy, i, j, shift, f);
+    if (g.ybc == YBC_WALLS) {
+        if (j == 0) {
+            store_node_d<ST, SS>(b, copy, i, -1, shift, f);
+            store_node_d<ST, SS>(b, copy, i, -2, shift, f);
+        }
+        if (j == g.ny) {
+            store_node_d<ST, SS>(b, copy, i, g.ny + 1, shift, f);
+            store_node_d<ST, SS>(b, copy, i, g.ny + 2, shift, f);
+        }
+    } else {
+        if (j < 2) store_node_d<ST, SS>(b, copy, i, j + g.nrow, shift, f);
+        if (j >= g.nrow - 2) store_node_d<ST, SS>(b, copy, i, j - g.nrow, shift, f);
+    }
+    if (g.xbc == XBC_PERIODIC) {
+        if (i < 2) store_node_d<ST, SS>(b, copy, i + g.nx, j, shift, f);
+        if (i >= g.nx - 2) store_node_d<ST, SS>(b, copy, i - g.nx, j, shift, f);
+    } else if (i == 0 || i == g.nx - 1) {
+        double rho, ux, uy, eb[SS::Q], en[SS::Q], gq[SS::Q];
+        moments_d<SS>(f, rho, ux, uy);
+        feq_d<SS>(i == 0 ? ph.rho_in : ph.rho_out, ux, uy, eb);
+        feq_d<SS>(rho, ux, uy, en);
+#pragma unroll
+        for (int a = 0; a < SS::Q; ++a) gq[a] = eb[a] + (f[a] - en[a]);
+        if (i == 0) {
+            store_node_d<ST, SS>(b, copy, -1, j, shift, gq);
+            store_node_d<ST, SS>(b, copy, -2, j, shift, gq);
+        } else {
+            store_node_d<ST, SS>(b, copy, g.nx, j, shift, gq);
+            store_node_d<ST, SS>(b, copy, g.nx + 1, j, shift, gq);
+        }
+    }
+}
+
+// Everything a node of set SS owes the next step besides its own entry:
+// images, and (Hermite interface) its projection into the partner set OO
+// wherever a stencil of OO reads it.
+template <class ST, class SS, class OO>
+__device__ void finish_node(const Buf &self, const Buf &other, int copy, int i, int j, double shift,
+                            const double *f, bool own, bool proj, const Geo &g, const Phys &ph) {
+    emit_node<ST, SS>(self, copy, i, j, shift, f, own, g, ph);
+    if constexpr (OO::Q > 0) {
+        if (proj) {
+            double fo[OO::Q];
+            project_d<SS, OO>(f, fo, nullptr);
+            emit_node<ST, OO>(other, copy, i, j, shift, fo, true, g, ph);
+        }
+    }
+}
+
+// ------------------------------------------------------------- hot kernel
+// One time step of set SS.  Work item = 64 columns [i0, i0+64) x rows
+// [j0, j1), all evolved in SS.  Reads copy `cur`, writes copy `cur ^ 1`.
+template <class ST, class SS, class OO>
+__global__ __launch_bounds__(64) void k_update(const StepArgs A) {
+    using T = typename ST::M;
+    using SV = typename ST::S;
+    using TB = typename SS::T;
+    constexpr int N = SS::N, Q = SS::Q, EQ = SS::EQ;
+
+    // XCD-aware mapping: consecutive items (neighbouring strips) go to
+    // blocks that the dispatcher places on the same XCD (block b -> XCD b % 8)
+    const int b = blockIdx.x;
+    const int it = (b & 7) * A.chunk + (b >> 3);
+    if (it >= A.nitems) return;
+    const int i0 = A.items[4 * it], j0 = A.items[4 * it + 1], j1 = A.items[4 * it + 2];
+    const Geo &g = A.g;
+    const int lane = threadIdx.x;
+    const int nx = g.nx;
+    const int i = i0 + lane;
+    const bool valid = i < nx;
+    // Addressing: raw buffer access with one descriptor per copy, the lane's
+    // 32-bit byte offset (counted from column -2) in a vector register and
+    // the wave-uniform offset of (population, row) in a scalar register.
+    // Lanes that must not load or store get an offset past the end of the
+    // buffer, which the hardware turns into a zero load / dropped store.
+    constexpr unsigned EB = sizeof(SV);
+    const int64_t P = A.self.plane;
+    const int64_t pitch = A.self.pitch;
+    const int64_t rb = A.self.rowbase - 2;
+    const unsigned nbytes = unsigned(int64_t(Q) * P * EB);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A.self.base[A.cur], 0, int(nbytes), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rd =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A.self.base[A.cur ^ 1], 0, int(nbytes), 0x00020000);
+    const unsigned OOB = nbytes;
+    const unsigned vl = unsigned((i < nx + 1 ? i : nx + 1) + 2) * EB;
+    // halo columns: lane 0 <- i0-1, lane 1 <- i0-2, lane 62 <- i0+65, lane 63 <- i0+64
+    int ih;
+    if (lane == 0) ih = i0 - 1;
+    else if (lane == 1) ih = i0 - 2;
+    else if (lane == 62) ih = min(i0 + 65, nx + 1);
+    else ih = min(i0 + 64, nx + 1);
+    const unsigned vh = (lane < 2 || lane >= 62) ? unsigned(ih + 2) * EB : OOB;
+    const unsigned vs = valid ? unsigned(i + 2) * EB : OOB;
+#define LB_SOFF(a, j) unsigned(((int64_t)(a) * P + rb + (int64_t)((j) + 2) * pitch) * EB)
+
+    // per-abscissa constants nu_p = x_p dt and k_p = |nu_p|(1 - |nu_p|)/2
+    T nu[N], kk[N];
+#pragma unroll
+    for (int p = 0; p < N; ++p) {
+        if constexpr (sizeof(T) == 8) {
+            nu[p] = A.ks.nu[p];
+            kk[p] = A.ks.kk[p];
+        } else {
+            nu[p] = A.ks.nuf[p];
+            kk[p] = A.ks.kkf[p];
+        }
+    }
+
+    // y window per population: c = f_j; for xi_y > 0: s1 = f_j - f_{j-1},
+    // s2 = minmod(f_{j-1} - f_{j-2}, f_j - f_{j-1}); for xi_y < 0:
+    // s1 = f_{j+1}, s2 = minmod(f_{j+1} - f_j, f_j - f_{j-1})
+    T c[Q], s1[Q], s2[Q];
+#pragma unroll
+    for (int a = 0; a < Q; ++a) {
+        const double xq = TB::rule.x[a / N];
+        if (xq > 0.0) {
+            T fm2 = ST::bld(rs, vl, LB_SOFF(a, j0 - 2));
+            T fm1 = ST::bld(rs, vl, LB_SOFF(a, j0 - 1));
+            T f0 = ST::bld(rs, vl, LB_SOFF(a, j0));
+            c[a] = f0;
+            s1[a] = f0 - fm1;
+            s2[a] = minmod(fm1 - fm2, f0 - fm1);
+        } else if (xq < 0.0) {
+            T fm1 = ST::bld(rs, vl, LB_SOFF(a, j0 - 1));
+            T f0 = ST::bld(rs, vl, LB_SOFF(a, j0));
+            T fp1 = ST::bld(rs, vl, LB_SOFF(a, j0 + 1));
+            c[a] = f0;
+            s1[a] = fp1;
+            s2[a] = minmod(fp1 - f0, f0 - fm1);
+        } else {
+            c[a] = ST::bld(rs, vl, LB_SOFF(a, j0));
+            s1[a] = T(0);
+            s2[a] = T(0);
+        }
+    }
+
+    // periodic images of the first/last two columns are written here; wall
+    // rows, row images, pressure columns and partner-set projections are
+    // finished afterwards by k_finish
+    const bool per_x = g.xbc == XBC_PERIODIC;
+    const bool wave_img = per_x && (i0 < 2 || i0 + 64 > nx - 2);   // uniform
+    const unsigned vimg_lo = (per_x && valid && i < 2) ? unsigned(i + nx + 2) * EB : OOB;
+    const unsigned vimg_hi = (per_x && valid && i >= nx - 2) ? unsigned(i - nx + 2) * EB : OOB;
+
+    const T rho_shift = T(A.rho_shift);
+    const T om0 = T(A.ph.omega0);
+    const T om_rho = T(A.ph.omega0 / A.ph.rho_ref);
+    const T dtT = T(A.ph.dt), gxT = T(A.ph.gx), gyT = T(A.ph.gy);
+
+    for (int j = j0; j < j1; ++j) {
+        // new rows of the y window and this row's x halo
+        T nw[Q], hr[Q];
+#pragma unroll
+        for (int a = 0; a < Q; ++a) {
+            const double xq = TB::rule.x[a / N];
+            const int jn = xq < 0.0 ? j + 2 : j + 1;
+            nw[a] = ST::bld(rs, vl, LB_SOFF(a, jn));
+            hr[a] = ST::bld(rs, vh, LB_SOFF(a, j));
+        }
+
+        // moments of the centre values: rho' = sum f (shifted), j = sum xi f
+        T rp = T(0), jx = T(0), jy = T(0);
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            T sq = T(0), sxq = T(0);
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                sq += c[p + N * q];
+                sxq += T(TB::rule.x[p]) * c[p + N * q];
+            }
+            rp += sq;
+            jx += sxq;
+            jy += T(TB::rule.x[q]) * sq;
+        }
+        const T rho = rho_shift + rp;
+        const T inv = T(1) / rho;
+        const T ux = jx * inv, uy = jy * inv;
+        const T om = A.ph.tau_mode == TAU_RHO ? om_rho * rho : om0;
+        const T omr = om * rho, Gx = dtT * rho * gxT, Gy = dtT * rho * gyT;
+        T px[EQ + 1], py[EQ + 1];
+        px[0] = py[0] = T(1);
+#pragma unroll
+        for (int k = 1; k <= EQ; ++k) {
+            px[k] = px[k - 1] * ux;
+            py[k] = py[k - 1] * uy;
+        }
+        // C_km: relaxation + force coefficient of He_k(x) He_m(y) / (k! m!)
+        T C[EQ + 1][EQ + 1];
+#pragma unroll
+        for (int k = 0; k <= EQ; ++k)
+#pragma unroll
+            for (int m = 0; m + k <= EQ; ++m) {
+                if (k == 0 && m == 0) {
+                    C[0][0] = om * rp;
+                } else {
+                    T v = omr * px[k] * py[m];
+                    if (k > 0) v += Gx * T(k) * px[k - 1] * py[m];
+                    if (m > 0) v += Gy * T(m) * px[k] * py[m - 1];
+                    C[k][m] = v;
+                }
+            }
+
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            // B_k(q) = w_q sum_m C_km He_m(x_q)/m!
+            T B[EQ + 1];
+#pragma unroll
+            for (int k = 0; k <= EQ; ++k) {
+                T s = T(0);
+#pragma unroll
+                for (int m = 0; m + k <= EQ; ++m) s += C[k][m] * T(TB::rule.w[q] * TB::hk.v[m][q]);
+                B[k] = s;
+            }
+            const double xq = TB::rule.x[q];
+#pragma unroll
+            for (int p = 0; p < N; ++p) {
+                const int a = p + N * q;
+                const double xp = TB::rule.x[p];
+                // source: (dt/tau) f_eq + dt g (shifted), separable in p and q
+                T Sa = T(0);
+#pragma unroll
+                for (int k = 0; k <= EQ; ++k) Sa += T(TB::rule.w[p] * TB::hk.v[k][p]) * B[k];
+                const T f = c[a];
+                T acc = f - om * f + Sa;
+
+                // x fluxes (DPP neighbours, halo at lanes 0 / 63)
+                if (xp != 0.0) {
+                    const T fm1 = dpp<DPP_WAVE_SHR1>(f, hr[a]);
+                    const T fp1 = dpp<DPP_WAVE_SHL1>(f, hr[a]);
+                    const T dm = f - fm1, dp = fp1 - f;
+                    if (xp > 0.0) {
+                        const T h2 = dpp<DPP_WAVE_SHL1>(hr[a], hr[a]);   // lane 0 <- f(i0-2)
+                        const T dmm = dpp<DPP_WAVE_SHR1>(dm, fm1 - h2);
+                        const T Lp = minmod(dm, dp), Lm = minmod(dmm, dm);
+                        acc = acc - nu[p] * dm - kk[p] * (Lp - Lm);
+                    } else {
+                        const T h2 = dpp<DPP_WAVE_SHR1>(hr[a], hr[a]);   // lane 63 <- f(i0+65)
+                        const T dpp_ = dpp<DPP_WAVE_SHL1>(dp, h2 - fp1);
+                        const T Lp = minmod(dpp_, dp), Lm = minmod(dp, dm);
+                        acc = acc - nu[p] * dp - kk[p] * (Lp - Lm);
+                    }
+                }
+                // y fluxes (register window)
+                if (xq > 0.0) {
+                    const T dp = nw[a] - f;
+                    const T Lp = minmod(s1[a], dp);
+                    acc = acc - nu[q] * s1[a] - kk[q] * (Lp - s2[a]);
+                    c[a] = nw[a];
+                    s1[a] = dp;
+                    s2[a] = Lp;
+                } else if (xq < 0.0) {
+                    const T d = s1[a] - f, dn = nw[a] - s1[a];
+                    const T Lp = minmod(dn, d);
+                    acc = acc - nu[q] * d - kk[q] * (Lp - s2[a]);
+                    c[a] = s1[a];
+                    s1[a] = nw[a];
+                    s2[a] = Lp;
+                } else {
+                    c[a] = nw[a];
+                }
+                ST::bst(rd, vs, LB_SOFF(a, j), acc);
+                if (wave_img) {
+                    ST::bst(rd, vimg_lo, LB_SOFF(a, j), acc);
+                    ST::bst(rd, vimg_hi, LB_SOFF(a, j), acc);
+                }
+            }
+        }
+
+    }
+#undef LB_SOFF
+}
+
+// Second pass of a step over the special nodes of both sets (list built on
+// the host when the regions change): entry = (i, j, set, flags) with flags
+// 1 = wall row, 2 = row image, 4 = pressure column, 8 = read by the partner
+// set.  A.self is the low set's buffer, A.other the high set's.
+template <class ST, class SS, class OO>
+__device__ void finish_entry(const Buf &self, const Buf &other, int copy, int i, int j, int flags,
+                             const StepArgs &A) {
+    double f[SS::Q];
+    load_node_d<ST, SS>(self, copy, i, j, A.rho_shift, f);
+    const bool wall = flags & 1;
+    if (wall) diffuse_wall_d<SS>(f, j == A.g.ny, A.ph);
+    finish_node<ST, SS, OO>(self, other, copy, i, j, A.rho_shift, f, wall, (flags & 8) != 0, A.g, A.ph);
+}
+
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_finish(const StepArgs A) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.nitems) return;
+    const int i = A.items[4 * k], j = A.items[4 * k + 1], set = A.items[4 * k + 2], flags = A.items[4 * k + 3];
+    const int copy = A.cur ^ 1;
+    if (set == 0) finish_entry<ST, LS, HS>(A.self, A.other, copy, i, j, flags, A);
+    else finish_entry<ST, HS, LS>(A.other, A.self, copy, i, j, flags, A);
+}
+
+// ------------------------------------------------------ per-node kernels
+__device__ __forceinline__ bool node_index(const Geo &g, int &i, int &j) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.nrow * g.nx) return false;
+    j = n / g.nx;
+    i = n - j * g.nx;
+    return true;
+}
+
+__device__ __forceinline__ bool owns(int r, bool self_high) {
+    return self_high ? r == REG_HIGH : r == REG_LOW;
+}
+
+// Rebuild all ghost, image and projection entries of copy `cur` from the
+// nodes' own entries (after initialisation, set_populations or a region
+// change).
+template <class ST, class SS, class OO>
+__global__ void k_refresh(const NodeArgs A) {
+    int i, j;
+    if (!node_index(A.g, i, j)) return;
+    int r = region_at(i, j, A.g);
+    if (!owns(r, A.self_high)) return;
+    double f[SS::Q];
+    load_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+    int t = tile_of(i, A.g);
+    bool proj = (OO::Q > 0) && A.g.iface == IF_HERMITE &&
+                neighbour_in(i, j, A.self_high ? REG_LOW : REG_HIGH, A.g.blo[t], A.g.bhi[t], A.g);
+    finish_node<ST, SS, OO>(A.self, A.other, A.cur, i, j, A.rho_shift, f, false, proj, A.g, A.ph);
+}
+
+// f = f_eq(rho, u) on the nodes of this set (in0..2 = rho, ux, uy fields)
+template <class ST, class SS, class OO>
+__global__ void k_init_eq(const NodeArgs A) {
+    int i, j;
+    if (!node_index(A.g, i, j)) return;
+    int r = region_at(i, j, A.g);
+    if (!owns(r, A.self_high)) return;
+    int n = j * A.g.nx + i;
+    double f[SS::Q];
+    feq_d<SS>(A.in0[n], A.in1[n], A.in2[n], f);
+    store_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+}
+
+// populations from an FP64 [Q][nrow][nx] array (own nodes and, for the low
+// set in the paper interface mode, the interface rows; the high set stores
+// interface rows too)
+template <class ST, class SS, class OO>
+__global__ void k_set_pop(const NodeArgs A) {
+    int i, j;
+    if (!node_index(A.g, i, j)) return;
+    int r = region_at(i, j, A.g);
+    if (!owns(r, A.self_high) && r != REG_IFACE) return;
+    const int64_t NN = (int64_t)A.g.nrow * A.g.nx;
+    double f[SS::Q];
+#pragma unroll
+    for (int a = 0; a < SS::Q; ++a) f[a] = A.in0[a * NN + j * A.g.nx + i];
+    store_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+}
+
+template <class ST, class SS, class OO>
+__global__ void k_get_pop(const NodeArgs A) {
+    int i, j;
+    if (!node_index(A.g, i, j)) return;
+    int r = region_at(i, j, A.g);
+    const int64_t NN = (int64_t)A.g.nrow * A.g.nx;
+    double f[SS::Q];
+    if (owns(r, A.self_high) || r == REG_IFACE) {
+        load_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+    } else {
+#pragma unroll
+        for (int a = 0; a < SS::Q; ++a) f[a] = __builtin_nan("");
+    }
+#pragma unroll
+    for (int a = 0; a < SS::Q; ++a) A.out0[a * NN + j * A.g.nx + i] = f[a];
+}
+
+// rho, ux, uy of the nodes of this set (the low set also reports the
+// interface rows, whose representations all carry rho_I, u_I)
+template <class ST, class SS, class OO>
+__global__ void k_moments(const NodeArgs A) {
+    int i, j;
+    if (!node_index(A.g, i, j)) return;
+    int r = region_at(i, j, A.g);
+    if (!(owns(r, A.self_high) || (!A.self_high && r == REG_IFACE))) return;
+    double f[SS::Q], rho, ux, uy;
+    load_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+    moments_d<SS>(f, rho, ux, uy);
+    int n = j * A.g.nx + i;
+    A.out0[n] = rho;
+    A.out1[n] = ux;
+    A.out2[n] = uy;
+}
+
+// non-equilibrium indicator: max over (2,0), (1,1), (0,2) of
+// |a_km - rho ux^k uy^m| / rho
+template <class ST, class SS, class OO>
+__global__ void k_indicator(const NodeArgs A) {
+    int i, j;
+    if (!node_index(A.g, i, j)) return;
+    int r = region_at(i, j, A.g);
+    if (!(owns(r, A.self_high) || (!A.self_high && r == REG_IFACE))) return;
+    using TB = typename SS::T;
+    constexpr int N = SS::N;
+    double f[SS::Q];
+    load_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+    double a00 = 0, a10 = 0, a01 = 0, a20 = 0, a11 = 0, a02 = 0;
+#pragma unroll
+    for (int a = 0; a < SS::Q; ++a) {
+        double hx1 = TB::he.v[1][a % N], hy1 = TB::he.v[1][a / N];
+        double hx2 = TB::he.v[2][a % N], hy2 = TB::he.v[2][a / N];
+        a00 += f[a];
+        a10 += f[a] * hx1;
+        a01 += f[a] * hy1;
+        a20 += f[a] * hx2;
+        a11 += f[a] * hx1 * hy1;
+        a02 += f[a] * hy2;
+    }
+    double rho = a00, ux = a10 / rho, uy = a01 / rho;
+    double b = fabs(a20 - rho * ux * ux) / rho;
+    b = fmax(b, fabs(a11 - rho * ux * uy) / rho);
+    b = fmax(b, fabs(a02 - rho * uy * uy) / rho);
+    A.out0[j * A.g.nx + i] = b;
+}
+
+// region change: nodes now in this set that were in the partner set get
+// the projection of their partner-set populations (lift or restriction)
+template <class ST, class SS, class OO>
+__global__ void k_convert(const NodeArgs A) {
+    if constexpr (OO::Q > 0) {
+        int i, j;
+        if (!node_index(A.g, i, j)) return;
+        int r1 = region_at(i, j, A.g);
+        if (!owns(r1, A.self_high)) return;
+        int t = tile_of(i, A.g);
+        int r0 = reg_of(A.oblo[t], A.obhi[t], j, A.g);
+        if (!owns(r0, !A.self_high)) return;
+        double fo[OO::Q], fs[SS::Q];
+        load_node_d<ST, OO>(A.other, A.cur, i, j, A.rho_shift, fo);
+        const double *cl = nullptr;
+        if (A.closure && A.self_high) cl = A.closure + (int64_t)(j * A.g.nx + i) * SS::Q;
+        project_d<OO, SS>(fo, fs, cl);
+        store_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, fs);
+    }
+}
+
+// Interface rows of the interpolation/extrapolation mode (Sec. 2.2): one
+// thread per column and interface.  rho_I, u_I = averages of the low-side
+// neighbour l and high-side neighbour h; in each set the population is the
+// equilibrium at (rho_I, u_I) plus the same-side neighbour's
+// non-equilibrium part.  The row beyond I on each side gets a copy of I in
+// the other side's set (the second stencil row).  `recompute` = 0 keeps
+// the stored I rows and only rebuilds copies and images.
+template <class ST, class LS, class HS>
+__global__ void k_paper_iface(const NodeArgs A, int copy, int recompute) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= 2 * A.g.nx) return;
+    const int i = n % A.g.nx, top = n / A.g.nx;
+    const int t = tile_of(i, A.g);
+    const int lo = A.g.blo[t], hi = A.g.bhi[t];
+    int jI, jl, jh;
+    if (!top) {
+        if (lo <= 0) return;
+        jI = lo;
+        jl = lo + 1;
+        jh = lo - 1;
+    } else {
+        if (hi <= 0) return;
+        jI = A.g.ny - hi;
+        jl = jI - 1;
+        jh = jI + 1;
+    }
+    const Buf &BL = A.self, &BH = A.other;
+    double fL[LS::Q], fH[HS::Q];
+    if (recompute) {
+        double fl[LS::Q], fh[HS::Q], e1[HS::Q > LS::Q ? HS::Q : LS::Q], e2[HS::Q > LS::Q ? HS::Q : LS::Q];
+        load_node_d<ST, LS>(BL, copy, i, jl, A.rho_shift, fl);
+        load_node_d<ST, HS>(BH, copy, i, jh, A.rho_shift, fh);
+        double rl, uxl, uyl, rh, uxh, uyh;
+        moments_d<LS>(fl, rl, uxl, uyl);
+        moments_d<HS>(fh, rh, uxh, uyh);
+        double rI = 0.5 * (rl + rh), uxI = 0.5 * (uxl + uxh), uyI = 0.5 * (uyl + uyh);
+        feq_d<LS>(rI, uxI, uyI, e1);
+        feq_d<LS>(rl, uxl, uyl, e2);
+#pragma unroll
+        for (int a = 0; a < LS::Q; ++a) fL[a] = e1[a] + (fl[a] - e2[a]);
+        feq_d<HS>(rI, uxI, uyI, e1);
+        feq_d<HS>(rh, uxh, uyh, e2);
+#pragma unroll
+        for (int a = 0; a < HS::Q; ++a) fH[a] = e1[a] + (fh[a] - e2[a]);
+    } else {
+        load_node_d<ST, LS>(BL, copy, i, jI, A.rho_shift, fL);
+        load_node_d<ST, HS>(BH, copy, i, jI, A.rho_shift, fH);
+    }
+    // I row in both sets, plus the copy beyond I on the opposite side
+    emit_node<ST, LS>(BL, copy, i, jI, A.rho_shift, fL, true, A.g, A.ph);
+    emit_node<ST, LS>(BL, copy, i, jh, A.rho_shift, fL, true, A.g, A.ph);
+    emit_node<ST, HS>(BH, copy, i, jI, A.rho_shift, fH, true, A.g, A.ph);
+    emit_node<ST, HS>(BH, copy, i, jl, A.rho_shift, fH, true, A.g, A.ph);
+}
+
+// Batched FP64 projection (test hook / closure training): n nodes, [node][Q]
+template <class SS, class DD>
+__global__ void k_project(const double *fs, const double *closure, double *fd, int64_t n) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double a[SS::Q], b[DD::Q];
+#pragma unroll
+    for (int q = 0; q < SS::Q; ++q) a[q] = fs[k * SS::Q + q];
+    project_d<SS, DD>(a, b, closure ? closure + k * DD::Q : nullptr);
+#pragma unroll
+    for (int q = 0; q < DD::Q; ++q) fd[k * DD::Q + q] = b[q];
+}
+
+}  // namespace lbk

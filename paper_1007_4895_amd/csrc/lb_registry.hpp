@@ -1,0 +1,37 @@
+// lb_registry.hpp -- table of compiled kernel instantiations.
+//
+// Each storage type has its own translation unit that instantiates the
+// kernels for the (self set, partner set) pairs it supports and exposes them
+// through one KernelSet per pair.  The host runtime looks pairs up here.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lb_internal.hpp"
+
+namespace lbk {
+
+using StepFn = void (*)(const lbi::StepArgs &, int grid, hipStream_t);
+using NodeFn = void (*)(const lbi::NodeArgs &, int grid, hipStream_t);
+using IfaceFn = void (*)(const lbi::NodeArgs &, int copy, int recompute, int grid, hipStream_t);
+using ProjFn = void (*)(const double *, const double *, double *, int64_t, hipStream_t);
+
+struct KernelSet {
+    int storage, nS, eqS, nO, eqO;
+    StepFn update;
+    StepFn finish;   // valid when `self` is the low set of the pair
+    NodeFn refresh, init_eq, set_pop, get_pop, moments, indicator, convert;
+    IfaceFn paper_iface;   // valid when `self` is the low set of the pair
+    ProjFn project;        // FP64 projection self -> partner
+    const void *update_kernel;   // the __global__ symbol (for attribute queries)
+};
+
+struct Registry {
+    const KernelSet *sets;
+    int count;
+};
+
+Registry registry_f64();
+Registry registry_f32();
+Registry registry_bf16();
+
+}  // namespace lbk

@@ -1,0 +1,916 @@
+// lb_runtime.hip -- host runtime behind include/lb.h.
+//
+// Owns no device memory: everything lives in the caller's workspace, carved
+// up by ws_layout().  All work is enqueued on the caller's stream.  A time
+// step is: one k_update launch per velocity set (work items = 64 columns x a
+// strip of rows of that set), then one k_finish launch over the list of
+// special nodes (walls, images, pressure columns, nodes the partner set
+// reads), then, in the interpolation/extrapolation interface mode, the
+// interface-row kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lb.h"
+#include "lb_internal.hpp"
+#include "lb_registry.hpp"
+#include "lb_tables.hpp"
+
+using namespace lbi;
+
+namespace {
+
+thread_local std::string g_err;
+
+lb_status fail(lb_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) return fail(LB_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+double xmax_of(int n) {
+    switch (n) {
+        case 3: return lbt::Tab<3>::xmax();
+        case 4: return lbt::Tab<4>::xmax();
+        case 6: return lbt::Tab<6>::xmax();
+    }
+    return 0.0;
+}
+
+void abscissae(int n, double *x, double *w) {
+    auto cp = [&](const auto &r) {
+        for (int p = 0; p < n; ++p) {
+            x[p] = r.x[p];
+            w[p] = r.w[p];
+        }
+    };
+    if (n == 3) cp(lbt::Tab<3>::rule);
+    if (n == 4) cp(lbt::Tab<4>::rule);
+    if (n == 6) cp(lbt::Tab<6>::rule);
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int esize_of(int storage) { return storage == LB_STORE_F64 ? 8 : storage == LB_STORE_F32 ? 4 : 2; }
+
+struct Layout {
+    int32_t pitch[2], rowbase[2];
+    int64_t plane[2];
+    size_t off_pop[2][2];   // [set][copy]
+    size_t off_blo, off_bhi, off_oblo, off_obhi;
+    size_t off_items[2], off_fin, off_stage, off_mom, off_part;
+    int maxitems, maxfin;
+    size_t stage_elems;
+    size_t total;
+};
+
+int ntiles_of(const lb_params &p) {
+    int tw = p.tile_w > 0 ? p.tile_w : p.nx;
+    return (p.nx + tw - 1) / tw;
+}
+
+Layout ws_layout(const lb_params &p) {
+    Layout L{};
+    const int eb = esize_of(p.storage);
+    const int al = 128 / eb;
+    const int nrow = p.ny + 1;
+    const int n[2] = {p.n_low, p.n_high};
+    size_t off = 0;
+    for (int s = 0; s < 2; ++s) {
+        L.pitch[s] = int32_t(align_up(size_t(p.nx) + 4, al));
+        L.rowbase[s] = al;
+        L.plane[s] = int64_t(align_up(size_t(al) + size_t(nrow + 4) * L.pitch[s], al));
+        size_t bytes = size_t(n[s] * n[s]) * size_t(L.plane[s]) * eb;
+        for (int c = 0; c < 2; ++c) {
+            L.off_pop[s][c] = off;
+            off = align_up(off + bytes, 256);
+        }
+    }
+    const int nt = ntiles_of(p);
+    const size_t nodes = size_t(nrow) * p.nx;
+    L.off_blo = off; off = align_up(off + 4 * nt, 256);
+    L.off_bhi = off; off = align_up(off + 4 * nt, 256);
+    L.off_oblo = off; off = align_up(off + 4 * nt, 256);
+    L.off_obhi = off; off = align_up(off + 4 * nt, 256);
+    const int ncolw = (p.nx + 63) / 64;
+    L.maxitems = ncolw * (nrow + 4);
+    for (int s = 0; s < 2; ++s) {
+        L.off_items[s] = off;
+        off = align_up(off + 16 * size_t(L.maxitems), 256);
+    }
+    L.maxfin = int(nodes);
+    L.off_fin = off; off = align_up(off + 16 * nodes, 256);
+    int qmax = std::max(std::max(n[0] * n[0], n[1] * n[1]), 3);
+    L.stage_elems = size_t(qmax) * nodes;
+    L.off_stage = off; off = align_up(off + 8 * L.stage_elems, 256);
+    L.off_mom = off; off = align_up(off + 8 * 3 * nodes, 256);
+    L.off_part = off; off = align_up(off + 8 * 3 * 1024, 256);
+    L.total = off;
+    return L;
+}
+
+const lbk::KernelSet *find_ks(int storage, int nS, int eqS, int nO, int eqO) {
+    lbk::Registry r = storage == LB_STORE_F64   ? lbk::registry_f64()
+                      : storage == LB_STORE_F32 ? lbk::registry_f32()
+                                                : lbk::registry_bf16();
+    for (int k = 0; k < r.count; ++k) {
+        const lbk::KernelSet &e = r.sets[k];
+        if (e.nS == nS && e.eqS == eqS && e.nO == nO && e.eqO == eqO) return &e;
+    }
+    return nullptr;
+}
+
+const lbk::KernelSet *find_any(int nS, int eqS, int nO, int eqO) {
+    for (int st = 0; st < 3; ++st)
+        if (auto k = find_ks(st, nS, eqS, nO, eqO)) return k;
+    return nullptr;
+}
+
+// region of node (i, j) for bands lo/hi of its tile; same rule as the kernels
+int host_reg(int lo, int hi, int j, int ny, int iface) {
+    if (j < lo || j > ny - hi) return REG_HIGH;
+    if (iface == IF_PAPER && ((lo > 0 && j == lo) || (hi > 0 && j == ny - hi))) return REG_IFACE;
+    return REG_LOW;
+}
+
+// ------------------------------------------------ generic (untemplated) kernels
+__global__ void k_sum3_partial(const double *a, const double *b, const double *c, int64_t n, double *part) {
+    __shared__ double sh[3][256];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+        double r = a[k];
+        s0 += r;
+        s1 += r * b[k];
+        s2 += r * c[k];
+    }
+    sh[0][threadIdx.x] = s0;
+    sh[1][threadIdx.x] = s1;
+    sh[2][threadIdx.x] = s2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) part[q * 1024 + blockIdx.x] = sh[q][0];
+}
+
+__global__ void k_sum3_final(double *part, int nb) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        for (int q = 0; q < 3; ++q) {
+            double s = 0.0;
+            for (int b = 0; b < nb; ++b) s += part[q * 1024 + b];
+            part[q * 1024] = s;
+        }
+    }
+}
+
+// Per-tile bands from the indicator: bottom band = 1 + highest lower-half
+// row with B > theta (mirrored at the top), clamped to [bmin, bmax].
+__global__ void k_bands(const double *B, Geo g, double theta, int bmin, int bmax, int32_t *blo, int32_t *bhi) {
+    __shared__ int slo, shi;
+    const int t = blockIdx.x;
+    if (threadIdx.x == 0) {
+        slo = 0;
+        shi = 0;
+    }
+    __syncthreads();
+    const int half = g.ny / 2;
+    const int c0 = t * g.tile_w, c1 = min(c0 + g.tile_w, g.nx);
+    const int w = c1 - c0;
+    int lo = 0, hi = 0;
+    for (int k = threadIdx.x; k < w * (half + 1); k += blockDim.x) {
+        int i = c0 + k % w, j = k / w;
+        if (B[(int64_t)j * g.nx + i] > theta) lo = max(lo, j + 1);
+        if (B[(int64_t)(g.ny - j) * g.nx + i] > theta) hi = max(hi, j + 1);
+    }
+    atomicMax(&slo, lo);
+    atomicMax(&shi, hi);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        blo[t] = min(max(slo, bmin), bmax);
+        bhi[t] = min(max(shi, bmin), bmax);
+    }
+}
+
+}  // namespace
+
+struct lb_lattice {
+    lb_params p;
+    hipStream_t stream;
+    char *ws;
+    Layout lay;
+    int n[2], eq[2], Q[2];
+    Buf buf[2];
+    SetK kconst[2];
+    const lbk::KernelSet *ks[2];
+    Geo geo;
+    Phys ph;
+    double dt, tau0, rho_shift;
+    int ntiles, tile_w, cur;
+    int64_t step;
+    bool initialized;
+    std::vector<int32_t> blo, bhi;
+    int32_t *d_blo, *d_bhi, *d_oblo, *d_obhi;
+    int32_t *d_items[2];
+    int nitems[2];
+    int32_t *d_fin;
+    int nfin;
+    int strip;
+    double *d_stage, *d_mom, *d_part;
+    bool timing;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used;
+    std::vector<int> ev_kind;   // per event pair: 1 = dominant update kernel, 0 = other update
+    int64_t count[3];           // nodes per region: low, high, interface rows
+    int dom;                    // set whose update moves the most bytes per step
+};
+
+namespace {
+
+NodeArgs node_args(const lb_lattice *L, int s, int copy) {
+    NodeArgs a{};
+    a.g = L->geo;
+    a.ph = L->ph;
+    a.self = L->buf[s];
+    a.other = L->buf[1 - s];
+    a.rho_shift = L->rho_shift;
+    a.cur = copy;
+    a.self_high = s;
+    a.which = s;
+    return a;
+}
+
+int node_grid(const lb_lattice *L) { return (L->geo.nrow * L->geo.nx + 255) / 256; }
+
+// work items of set s: maximal runs of rows of that set per 64-column wave,
+// cut into strips; the list is ordered column-major so neighbouring strips
+// are consecutive (and land on the same XCD through the kernel's mapping)
+int build_items(const lb_lattice *L, int s, std::vector<int32_t> &out) {
+    out.clear();
+    const int nx = L->p.nx, ny = L->p.ny, nrow = ny + 1;
+    const int want = s ? REG_HIGH : REG_LOW;
+    const int ncolw = (nx + 63) / 64;
+    int rows = 0;
+    std::vector<std::pair<int, int>> runs;
+    std::vector<int> runcol;
+    for (int w = 0; w < ncolw; ++w) {
+        const int i0 = 64 * w;
+        const int t = L->ntiles == 1 ? 0 : i0 / L->tile_w;
+        int j = 0;
+        while (j < nrow) {
+            if (host_reg(L->blo[t], L->bhi[t], j, ny, L->p.iface) != want) {
+                ++j;
+                continue;
+            }
+            int j1 = j;
+            while (j1 < nrow && host_reg(L->blo[t], L->bhi[t], j1, ny, L->p.iface) == want) ++j1;
+            runs.push_back({j, j1});
+            runcol.push_back(i0);
+            rows += j1 - j;
+            j = j1;
+        }
+    }
+    int strip = L->strip;
+    if (strip <= 0) strip = std::max(1, std::min(16, rows / 2048));
+    for (size_t r = 0; r < runs.size(); ++r)
+        for (int j = runs[r].first; j < runs[r].second; j += strip) {
+            out.push_back(runcol[r]);
+            out.push_back(j);
+            out.push_back(std::min(j + strip, runs[r].second));
+            out.push_back(0);
+        }
+    return int(out.size() / 4);
+}
+
+bool host_neighbour_in(const lb_lattice *L, int i, int j, int want) {
+    const int nx = L->p.nx, ny = L->p.ny, nrow = ny + 1;
+    auto reg = [&](int ii, int jj) {
+        int t = L->ntiles == 1 ? 0 : ii / L->tile_w;
+        return host_reg(L->blo[t], L->bhi[t], jj, ny, L->p.iface);
+    };
+    for (int d = -2; d <= 2; ++d) {
+        if (!d) continue;
+        int jj = j + d;
+        if (jj < 0 || jj > ny) {
+            if (L->p.ybc != LB_YBC_PERIODIC) continue;
+            jj = (jj + nrow) % nrow;
+        }
+        if (reg(i, jj) == want) return true;
+        int ii = i + d;
+        if (ii < 0 || ii >= nx) {
+            if (L->p.xbc != LB_XBC_PERIODIC) continue;
+            ii = (ii + nx) % nx;
+        }
+        if (reg(ii, j) == want) return true;
+    }
+    return false;
+}
+
+// special nodes of both sets: (i, j, set, flags) with flags 1 = wall,
+// 2 = row image, 4 = pressure column, 8 = read by the partner set
+int build_finish(const lb_lattice *L, std::vector<int32_t> &out) {
+    out.clear();
+    const int nx = L->p.nx, ny = L->p.ny, nrow = ny + 1;
+    for (int j = 0; j < nrow; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int t = L->ntiles == 1 ? 0 : i / L->tile_w;
+            int r = host_reg(L->blo[t], L->bhi[t], j, ny, L->p.iface);
+            if (r == REG_IFACE) continue;
+            int flags = 0;
+            if (L->p.ybc == LB_YBC_WALLS && (j == 0 || j == ny)) flags |= 1;
+            if (L->p.ybc == LB_YBC_PERIODIC && (j < 2 || j >= nrow - 2)) flags |= 2;
+            if (L->p.xbc == LB_XBC_PRESSURE && (i == 0 || i == nx - 1)) flags |= 4;
+            if (L->p.iface == LB_IFACE_HERMITE &&
+                host_neighbour_in(L, i, j, r == REG_HIGH ? REG_LOW : REG_HIGH))
+                flags |= 8;
+            if (flags) {
+                out.push_back(i);
+                out.push_back(j);
+                out.push_back(r == REG_HIGH ? 1 : 0);
+                out.push_back(flags);
+            }
+        }
+    return int(out.size() / 4);
+}
+
+lb_status upload_regions(lb_lattice *L) {
+    HIPCHK(hipMemcpyAsync(L->d_blo, L->blo.data(), 4 * L->ntiles, hipMemcpyHostToDevice, L->stream));
+    HIPCHK(hipMemcpyAsync(L->d_bhi, L->bhi.data(), 4 * L->ntiles, hipMemcpyHostToDevice, L->stream));
+    std::vector<int32_t> v;
+    for (int s = 0; s < 2; ++s) {
+        L->nitems[s] = build_items(L, s, v);
+        if (L->nitems[s] > L->lay.maxitems) return fail(LB_EINVAL, "too many work items");
+        if (L->nitems[s])
+            HIPCHK(hipMemcpyAsync(L->d_items[s], v.data(), v.size() * 4, hipMemcpyHostToDevice, L->stream));
+        HIPCHK(hipStreamSynchronize(L->stream));
+    }
+    for (int k = 0; k < 3; ++k) L->count[k] = 0;
+    for (int j = 0; j <= L->p.ny; ++j)
+        for (int t = 0; t < L->ntiles; ++t) {
+            int w = std::min(L->tile_w, L->p.nx - t * L->tile_w);
+            L->count[host_reg(L->blo[t], L->bhi[t], j, L->p.ny, L->p.iface)] += w;
+        }
+    L->dom = double(L->Q[1]) * L->count[1] > double(L->Q[0]) * L->count[0] ? 1 : 0;
+    L->nfin = build_finish(L, v);
+    if (L->nfin) HIPCHK(hipMemcpyAsync(L->d_fin, v.data(), v.size() * 4, hipMemcpyHostToDevice, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return LB_OK;
+}
+
+lb_status check_bands(const lb_lattice *L, const int32_t *lo, const int32_t *hi) {
+    for (int t = 0; t < L->ntiles; ++t) {
+        if (lo[t] < 0 || hi[t] < 0 || lo[t] > L->p.ny + 1 || hi[t] > L->p.ny + 1)
+            return fail(LB_EINVAL, "band out of range in tile %d", t);
+        if (L->p.iface == LB_IFACE_PAPER) {
+            if (lo[t] != lo[0] || hi[t] != hi[0])
+                return fail(LB_EINVAL, "the interpolation interface needs the same bands in every tile");
+            if (lo[t] + hi[t] + 3 > L->p.ny + 1 && (lo[t] > 0 || hi[t] > 0))
+                return fail(LB_EINVAL, "bands leave no low-order rows between the interface rows");
+        }
+    }
+    return LB_OK;
+}
+
+void set_geo(lb_lattice *L) {
+    L->geo.nx = L->p.nx;
+    L->geo.ny = L->p.ny;
+    L->geo.nrow = L->p.ny + 1;
+    L->geo.tile_w = L->tile_w;
+    L->geo.ntiles = L->ntiles;
+    L->geo.xbc = L->p.xbc;
+    L->geo.ybc = L->p.ybc;
+    L->geo.iface = L->p.iface;
+    L->geo.blo = L->d_blo;
+    L->geo.bhi = L->d_bhi;
+}
+
+lb_status refresh_all(lb_lattice *L, int recompute_iface) {
+    const int grid = node_grid(L);
+    for (int s = 0; s < 2; ++s) L->ks[s]->refresh(node_args(L, s, L->cur), grid, L->stream);
+    if (L->p.iface == LB_IFACE_PAPER)
+        L->ks[0]->paper_iface(node_args(L, 0, L->cur), L->cur, recompute_iface, (2 * L->p.nx + 255) / 256,
+                              L->stream);
+    HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+hipEvent_t next_event(lb_lattice *L) {
+    if (L->ev_used == L->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        L->ev_pool.push_back(e);
+    }
+    return L->ev_pool[L->ev_used++];
+}
+
+lb_status one_step(lb_lattice *L) {
+    StepArgs a{};
+    a.g = L->geo;
+    a.ph = L->ph;
+    a.rho_shift = L->rho_shift;
+    a.cur = L->cur;
+    for (int s = 0; s < 2; ++s) {
+        if (!L->nitems[s]) continue;
+        a.self = L->buf[s];
+        a.other = L->buf[1 - s];
+        a.ks = L->kconst[s];
+        a.self_high = s;
+        a.items = L->d_items[s];
+        a.nitems = L->nitems[s];
+        a.chunk = (a.nitems + 7) / 8;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (L->timing) {
+            e0 = next_event(L);
+            e1 = next_event(L);
+            if (!e0 || !e1) return fail(LB_EDEVICE, "event creation failed");
+            L->ev_kind.push_back(s == L->dom ? 1 : 0);
+            HIPCHK(hipEventRecord(e0, L->stream));
+        }
+        L->ks[s]->update(a, 8 * a.chunk, L->stream);
+        if (L->timing) HIPCHK(hipEventRecord(e1, L->stream));
+    }
+    if (L->nfin) {
+        a.self = L->buf[0];
+        a.other = L->buf[1];
+        a.items = L->d_fin;
+        a.nitems = L->nfin;
+        L->ks[0]->finish(a, (L->nfin + 127) / 128, L->stream);
+    }
+    if (L->p.iface == LB_IFACE_PAPER)
+        L->ks[0]->paper_iface(node_args(L, 0, L->cur ^ 1), L->cur ^ 1, 1, (2 * L->p.nx + 255) / 256, L->stream);
+    L->cur ^= 1;
+    L->step++;
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lb_last_error(void) { return g_err.c_str(); }
+
+lb_status lb_params_default(lb_params *p) {
+    if (!p) return fail(LB_EINVAL, "null params");
+    memset(p, 0, sizeof(*p));
+    p->nx = 64;
+    p->ny = 64;
+    p->n_low = p->n_high = 3;
+    p->eq_low = p->eq_high = 2;
+    p->tau_mode = LB_TAU_CONST;
+    p->xbc = LB_XBC_PERIODIC;
+    p->ybc = LB_YBC_WALLS;
+    p->iface = LB_IFACE_HERMITE;
+    p->storage = LB_STORE_F64;
+    p->kn = 0.1;
+    p->rho_ref = 1.0;
+    p->cfl = 0.5;
+    p->rho_in = p->rho_out = 1.0;
+    return LB_OK;
+}
+
+static lb_status validate(const lb_params *p) {
+    if (!p) return fail(LB_EINVAL, "null params");
+    if (p->nx < 2 || p->ny < 4) return fail(LB_EINVAL, "lattice too small (nx >= 2, ny >= 4)");
+    if (size_t(p->nx) * size_t(p->ny + 1) > (size_t(1) << 31)) return fail(LB_EINVAL, "lattice too large");
+    const int n[2] = {p->n_low, p->n_high}, eq[2] = {p->eq_low, p->eq_high};
+    const int fo[2] = {p->force_low, p->force_high};
+    for (int s = 0; s < 2; ++s) {
+        if (n[s] != 3 && n[s] != 4 && n[s] != 6)
+            return fail(LB_EUNSUPPORTED, "velocity set with %d points per axis not built (3, 4, 6)", n[s]);
+        // quadrature of degree 2n-1 resolves the equilibrium up to order n-1
+        if (eq[s] < 1 || eq[s] > n[s] - 1)
+            return fail(LB_EINVAL, "equilibrium order %d outside [1, %d] for D2Q%d", eq[s], n[s] - 1, n[s] * n[s]);
+        if (fo[s] != 0 && fo[s] != eq[s])
+            return fail(LB_EUNSUPPORTED, "force order must equal the equilibrium order");
+    }
+    if (p->storage < 0 || p->storage > 2) return fail(LB_EINVAL, "bad storage");
+    if (p->iface != LB_IFACE_HERMITE && p->iface != LB_IFACE_PAPER) return fail(LB_EINVAL, "bad interface");
+    if (p->xbc != LB_XBC_PERIODIC && p->xbc != LB_XBC_PRESSURE) return fail(LB_EINVAL, "bad xbc");
+    if (p->ybc != LB_YBC_WALLS && p->ybc != LB_YBC_PERIODIC) return fail(LB_EINVAL, "bad ybc");
+    if (p->tau_mode != LB_TAU_CONST && p->tau_mode != LB_TAU_RHO) return fail(LB_EINVAL, "bad tau mode");
+    if (!(p->kn > 0) || !(p->rho_ref > 0)) return fail(LB_EINVAL, "kn and rho_ref must be positive");
+    const int tw = p->tile_w > 0 ? p->tile_w : p->nx;
+    if (tw != p->nx && tw % 64 != 0) return fail(LB_EINVAL, "tile_w must be a multiple of 64 (or nx)");
+    if (p->xbc == LB_XBC_PRESSURE && p->nx < 4) return fail(LB_EINVAL, "pressure boundary needs nx >= 4");
+    const double xm = std::max(xmax_of(n[0]), xmax_of(n[1]));
+    double dt = p->dt > 0 ? p->dt : p->cfl * (1.0 / xm);
+    if (p->dt <= 0 && !(p->cfl > 0 && p->cfl <= 0.5)) return fail(LB_EINVAL, "cfl must be in (0, 0.5]");
+    if (dt * xm > 1.0 + 1e-12) return fail(LB_EINVAL, "Courant number above 1");
+    const double tau0 = p->kn * p->ny;
+    if (dt > tau0) return fail(LB_EINVAL, "time step %g above the relaxation time %g", dt, tau0);
+    Layout L = ws_layout(*p);
+    for (int s = 0; s < 2; ++s)
+        if (int64_t(n[s] * n[s]) * L.plane[s] * esize_of(p->storage) >= (int64_t(1) << 31))
+            return fail(LB_EINVAL, "one set's populations exceed 2 GiB per copy");
+    const int st = p->storage;
+    if (!find_ks(st, n[0], eq[0], n[1], eq[1]) || !find_ks(st, n[1], eq[1], n[0], eq[0]))
+        return fail(LB_EUNSUPPORTED, "no kernels built for D2Q%d(order %d)/D2Q%d(order %d) with storage %d",
+                    n[0] * n[0], eq[0], n[1] * n[1], eq[1], st);
+    return LB_OK;
+}
+
+size_t lb_workspace_bytes(const lb_params *p) {
+    if (validate(p) != LB_OK) return 0;
+    return ws_layout(*p).total;
+}
+
+lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t bytes, void *hip_stream,
+                            lb_lattice **out) {
+    if (!out) return fail(LB_EINVAL, "null output handle");
+    *out = nullptr;
+    lb_status st = validate(p);
+    if (st != LB_OK) return st;
+    Layout lay = ws_layout(*p);
+    if (!dev_workspace || bytes < lay.total)
+        return fail(LB_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, lay.total);
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % 256) return fail(LB_EINVAL, "workspace not 256-byte aligned");
+    lb_lattice *L = new lb_lattice();
+    L->p = *p;
+    L->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    L->ws = reinterpret_cast<char *>(dev_workspace);
+    L->lay = lay;
+    L->n[0] = p->n_low;
+    L->n[1] = p->n_high;
+    L->eq[0] = p->eq_low;
+    L->eq[1] = p->eq_high;
+    for (int s = 0; s < 2; ++s) {
+        L->Q[s] = L->n[s] * L->n[s];
+        for (int c = 0; c < 2; ++c) L->buf[s].base[c] = L->ws + lay.off_pop[s][c];
+        L->buf[s].plane = lay.plane[s];
+        L->buf[s].pitch = lay.pitch[s];
+        L->buf[s].rowbase = lay.rowbase[s];
+    }
+    L->ks[0] = find_ks(p->storage, L->n[0], L->eq[0], L->n[1], L->eq[1]);
+    L->ks[1] = find_ks(p->storage, L->n[1], L->eq[1], L->n[0], L->eq[0]);
+    const double xm = std::max(xmax_of(L->n[0]), xmax_of(L->n[1]));
+    L->dt = p->dt > 0 ? p->dt : p->cfl * (1.0 / xm);
+    L->tau0 = p->kn * p->ny;
+    L->rho_shift = p->storage == LB_STORE_F64 ? 0.0 : p->rho_ref;
+    L->tile_w = p->tile_w > 0 ? p->tile_w : p->nx;
+    L->ntiles = ntiles_of(*p);
+    for (int s = 0; s < 2; ++s) {
+        double x[8] = {0}, w[8] = {0};
+        abscissae(L->n[s], x, w);
+        for (int q = 0; q < 8; ++q) {
+            double nu = x[q] * L->dt, an = std::fabs(nu);
+            L->kconst[s].nu[q] = nu;
+            L->kconst[s].kk[q] = 0.5 * an * (1.0 - an);
+            L->kconst[s].nuf[q] = float(nu);
+            L->kconst[s].kkf[q] = float(0.5 * an * (1.0 - an));
+        }
+    }
+    L->ph = Phys{};
+    L->ph.dt = L->dt;
+    L->ph.omega0 = L->dt / L->tau0;
+    L->ph.rho_ref = p->rho_ref;
+    L->ph.rho_in = p->rho_in;
+    L->ph.rho_out = p->rho_out;
+    L->ph.gx = p->gx;
+    L->ph.gy = p->gy;
+    for (int k = 0; k < 4; ++k) L->ph.uw[k] = p->u_wall[k];
+    L->ph.tau_mode = p->tau_mode;
+    L->d_blo = reinterpret_cast<int32_t *>(L->ws + lay.off_blo);
+    L->d_bhi = reinterpret_cast<int32_t *>(L->ws + lay.off_bhi);
+    L->d_oblo = reinterpret_cast<int32_t *>(L->ws + lay.off_oblo);
+    L->d_obhi = reinterpret_cast<int32_t *>(L->ws + lay.off_obhi);
+    for (int s = 0; s < 2; ++s) L->d_items[s] = reinterpret_cast<int32_t *>(L->ws + lay.off_items[s]);
+    L->d_fin = reinterpret_cast<int32_t *>(L->ws + lay.off_fin);
+    L->d_stage = reinterpret_cast<double *>(L->ws + lay.off_stage);
+    L->d_mom = reinterpret_cast<double *>(L->ws + lay.off_mom);
+    L->d_part = reinterpret_cast<double *>(L->ws + lay.off_part);
+    L->strip = 0;
+    L->cur = 0;
+    L->step = 0;
+    L->blo.assign(L->ntiles, 0);
+    L->bhi.assign(L->ntiles, 0);
+    set_geo(L);
+    st = upload_regions(L);
+    if (st != LB_OK) {
+        delete L;
+        return st;
+    }
+    *out = L;
+    return LB_OK;
+}
+
+void lb_destroy_lattice(lb_lattice *L) {
+    if (!L) return;
+    for (auto e : L->ev_pool) (void)hipEventDestroy(e);
+    delete L;
+}
+
+lb_status lb_get_info(const lb_lattice *L, double *dt, double *tau0, int32_t *ntiles) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    if (dt) *dt = L->dt;
+    if (tau0) *tau0 = L->tau0;
+    if (ntiles) *ntiles = L->ntiles;
+    return LB_OK;
+}
+
+lb_status lb_set_regions(lb_lattice *L, const int32_t *lo, const int32_t *hi) {
+    if (!L || !lo || !hi) return fail(LB_EINVAL, "null argument");
+    lb_status st = check_bands(L, lo, hi);
+    if (st != LB_OK) return st;
+    L->blo.assign(lo, lo + L->ntiles);
+    L->bhi.assign(hi, hi + L->ntiles);
+    st = upload_regions(L);
+    if (st != LB_OK) return st;
+    if (L->initialized) return refresh_all(L, 1);
+    return LB_OK;
+}
+
+lb_status lb_get_regions(const lb_lattice *L, int32_t *lo, int32_t *hi) {
+    if (!L || !lo || !hi) return fail(LB_EINVAL, "null argument");
+    std::copy(L->blo.begin(), L->blo.end(), lo);
+    std::copy(L->bhi.begin(), L->bhi.end(), hi);
+    return LB_OK;
+}
+
+lb_status lb_region_counts(const lb_lattice *L, int64_t counts[3]) {
+    if (!L || !counts) return fail(LB_EINVAL, "null argument");
+    for (int k = 0; k < 3; ++k) counts[k] = L->count[k];
+    return LB_OK;
+}
+
+lb_status lb_set_strip_rows(lb_lattice *L, int32_t rows) {
+    if (!L || rows < 0 || rows > 1024) return fail(LB_EINVAL, "strip rows in [0, 1024] (0 = automatic)");
+    L->strip = rows;
+    return upload_regions(L);
+}
+
+lb_status lb_init_equilibrium(lb_lattice *L, const double *rho, const double *ux, const double *uy) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    const size_t N = size_t(L->p.ny + 1) * L->p.nx;
+    std::vector<double> h(3 * N);
+    for (size_t k = 0; k < N; ++k) {
+        h[k] = rho ? rho[k] : L->p.rho_ref;
+        h[N + k] = ux ? ux[k] : 0.0;
+        h[2 * N + k] = uy ? uy[k] : 0.0;
+    }
+    HIPCHK(hipMemcpyAsync(L->d_stage, h.data(), 8 * 3 * N, hipMemcpyHostToDevice, L->stream));
+    const int grid = node_grid(L);
+    for (int s = 0; s < 2; ++s) {
+        NodeArgs a = node_args(L, s, L->cur);
+        a.in0 = L->d_stage;
+        a.in1 = L->d_stage + N;
+        a.in2 = L->d_stage + 2 * N;
+        L->ks[s]->init_eq(a, grid, L->stream);
+    }
+    lb_status st = refresh_all(L, 1);
+    if (st != LB_OK) return st;
+    HIPCHK(hipStreamSynchronize(L->stream));
+    L->initialized = true;
+    L->step = 0;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_lattice *L, int64_t nsteps) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    if (!L->initialized) return fail(LB_ESTATE, "lattice not initialised");
+    if (nsteps < 0) return fail(LB_EINVAL, "negative step count");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        lb_status st = one_step(L);
+        if (st != LB_OK) return st;
+    }
+    HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+int64_t lb_step_count(const lb_lattice *L) { return L ? L->step : -1; }
+
+lb_status lb_moments(lb_lattice *L, double *rho, double *ux, double *uy, int32_t on_device) {
+    if (!L || !rho || !ux || !uy) return fail(LB_EINVAL, "null argument");
+    if (!L->initialized) return fail(LB_ESTATE, "lattice not initialised");
+    const size_t N = size_t(L->p.ny + 1) * L->p.nx;
+    double *o[3] = {rho, ux, uy};
+    if (!on_device)
+        for (int k = 0; k < 3; ++k) o[k] = L->d_mom + k * N;
+    for (int s = 0; s < 2; ++s) {
+        NodeArgs a = node_args(L, s, L->cur);
+        a.out0 = o[0];
+        a.out1 = o[1];
+        a.out2 = o[2];
+        L->ks[s]->moments(a, node_grid(L), L->stream);
+    }
+    HIPCHK(hipGetLastError());
+    if (!on_device) {
+        HIPCHK(hipMemcpyAsync(rho, o[0], 8 * N, hipMemcpyDeviceToHost, L->stream));
+        HIPCHK(hipMemcpyAsync(ux, o[1], 8 * N, hipMemcpyDeviceToHost, L->stream));
+        HIPCHK(hipMemcpyAsync(uy, o[2], 8 * N, hipMemcpyDeviceToHost, L->stream));
+        HIPCHK(hipStreamSynchronize(L->stream));
+    }
+    return LB_OK;
+}
+
+lb_status lb_conservation(lb_lattice *L, double out[3]) {
+    if (!L || !out) return fail(LB_EINVAL, "null argument");
+    if (!L->initialized) return fail(LB_ESTATE, "lattice not initialised");
+    const size_t N = size_t(L->p.ny + 1) * L->p.nx;
+    for (int s = 0; s < 2; ++s) {
+        NodeArgs a = node_args(L, s, L->cur);
+        a.out0 = L->d_mom;
+        a.out1 = L->d_mom + N;
+        a.out2 = L->d_mom + 2 * N;
+        L->ks[s]->moments(a, node_grid(L), L->stream);
+    }
+    const int nb = int(std::min<size_t>(1024, (N + 255) / 256));
+    hipLaunchKernelGGL(k_sum3_partial, dim3(nb), dim3(256), 0, L->stream, L->d_mom, L->d_mom + N, L->d_mom + 2 * N,
+                       int64_t(N), L->d_part);
+    hipLaunchKernelGGL(k_sum3_final, dim3(1), dim3(64), 0, L->stream, L->d_part, nb);
+    HIPCHK(hipGetLastError());
+    double h[3];
+    for (int q = 0; q < 3; ++q)
+        HIPCHK(hipMemcpyAsync(&h[q], L->d_part + q * 1024, 8, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    for (int q = 0; q < 3; ++q) out[q] = h[q];
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2]))
+        return fail(LB_EUNSTABLE, "non-finite conservation sums after step %lld", (long long)L->step);
+    return LB_OK;
+}
+
+lb_status lb_get_populations(lb_lattice *L, int32_t which, double *host) {
+    if (!L || !host || which < 0 || which > 1) return fail(LB_EINVAL, "bad argument");
+    if (!L->initialized) return fail(LB_ESTATE, "lattice not initialised");
+    const size_t N = size_t(L->p.ny + 1) * L->p.nx;
+    NodeArgs a = node_args(L, which, L->cur);
+    a.out0 = L->d_stage;
+    L->ks[which]->get_pop(a, node_grid(L), L->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(host, L->d_stage, 8 * N * L->Q[which], hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return LB_OK;
+}
+
+lb_status lb_set_populations(lb_lattice *L, int32_t which, const double *host) {
+    if (!L || !host || which < 0 || which > 1) return fail(LB_EINVAL, "bad argument");
+    const size_t N = size_t(L->p.ny + 1) * L->p.nx;
+    HIPCHK(hipMemcpyAsync(L->d_stage, host, 8 * N * L->Q[which], hipMemcpyHostToDevice, L->stream));
+    NodeArgs a = node_args(L, which, L->cur);
+    a.in0 = L->d_stage;
+    L->ks[which]->set_pop(a, node_grid(L), L->stream);
+    lb_status st = refresh_all(L, 0);
+    if (st != LB_OK) return st;
+    HIPCHK(hipStreamSynchronize(L->stream));
+    L->initialized = true;
+    return LB_OK;
+}
+
+size_t lb_state_bytes(const lb_lattice *L) {
+    if (!L) return 0;
+    size_t b = 16;
+    for (int s = 0; s < 2; ++s) b += size_t(L->Q[s]) * L->buf[s].plane * esize_of(L->p.storage);
+    return b;
+}
+
+lb_status lb_get_state(lb_lattice *L, void *host, size_t bytes) {
+    if (!L || !host || bytes < lb_state_bytes(L)) return fail(LB_EINVAL, "bad state buffer");
+    char *h = reinterpret_cast<char *>(host);
+    int64_t hdr[2] = {L->step, L->initialized ? 1 : 0};
+    memcpy(h, hdr, 16);
+    size_t off = 16;
+    for (int s = 0; s < 2; ++s) {
+        size_t b = size_t(L->Q[s]) * L->buf[s].plane * esize_of(L->p.storage);
+        HIPCHK(hipMemcpyAsync(h + off, L->buf[s].base[L->cur], b, hipMemcpyDeviceToHost, L->stream));
+        off += b;
+    }
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return LB_OK;
+}
+
+lb_status lb_set_state(lb_lattice *L, const void *host, size_t bytes) {
+    if (!L || !host || bytes < lb_state_bytes(L)) return fail(LB_EINVAL, "bad state buffer");
+    const char *h = reinterpret_cast<const char *>(host);
+    int64_t hdr[2];
+    memcpy(hdr, h, 16);
+    size_t off = 16;
+    for (int s = 0; s < 2; ++s) {
+        size_t b = size_t(L->Q[s]) * L->buf[s].plane * esize_of(L->p.storage);
+        HIPCHK(hipMemcpyAsync(L->buf[s].base[L->cur], h + off, b, hipMemcpyHostToDevice, L->stream));
+        off += b;
+    }
+    HIPCHK(hipStreamSynchronize(L->stream));
+    L->step = hdr[0];
+    L->initialized = hdr[1] != 0;
+    return LB_OK;
+}
+
+lb_status lb_indicator(lb_lattice *L, double *B, int32_t on_device) {
+    if (!L || !B) return fail(LB_EINVAL, "null argument");
+    if (!L->initialized) return fail(LB_ESTATE, "lattice not initialised");
+    const size_t N = size_t(L->p.ny + 1) * L->p.nx;
+    double *o = on_device ? B : L->d_mom;
+    for (int s = 0; s < 2; ++s) {
+        NodeArgs a = node_args(L, s, L->cur);
+        a.out0 = o;
+        L->ks[s]->indicator(a, node_grid(L), L->stream);
+    }
+    HIPCHK(hipGetLastError());
+    if (!on_device) {
+        HIPCHK(hipMemcpyAsync(B, o, 8 * N, hipMemcpyDeviceToHost, L->stream));
+        HIPCHK(hipStreamSynchronize(L->stream));
+    }
+    return LB_OK;
+}
+
+lb_status lb_change_regions(lb_lattice *L, const int32_t *lo, const int32_t *hi) {
+    if (!L || !lo || !hi) return fail(LB_EINVAL, "null argument");
+    if (!L->initialized) return lb_set_regions(L, lo, hi);
+    if (L->p.iface == LB_IFACE_PAPER) return fail(LB_EUNSUPPORTED, "region change with the interpolation interface");
+    lb_status st = check_bands(L, lo, hi);
+    if (st != LB_OK) return st;
+    HIPCHK(hipMemcpyAsync(L->d_oblo, L->d_blo, 4 * L->ntiles, hipMemcpyDeviceToDevice, L->stream));
+    HIPCHK(hipMemcpyAsync(L->d_obhi, L->d_bhi, 4 * L->ntiles, hipMemcpyDeviceToDevice, L->stream));
+    L->blo.assign(lo, lo + L->ntiles);
+    L->bhi.assign(hi, hi + L->ntiles);
+    st = upload_regions(L);
+    if (st != LB_OK) return st;
+    for (int s = 0; s < 2; ++s) {
+        NodeArgs a = node_args(L, s, L->cur);
+        a.oblo = L->d_oblo;
+        a.obhi = L->d_obhi;
+        L->ks[s]->convert(a, node_grid(L), L->stream);
+    }
+    st = refresh_all(L, 1);
+    if (st != LB_OK) return st;
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return LB_OK;
+}
+
+lb_status lb_update_regions(lb_lattice *L, double theta, int32_t bmin, int32_t bmax) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    if (bmin < 0 || bmax < bmin || bmax > L->p.ny / 2) return fail(LB_EINVAL, "bad band limits");
+    lb_status st = lb_indicator(L, L->d_mom, 1);
+    if (st != LB_OK) return st;
+    int32_t *nlo = L->d_oblo, *nhi = L->d_obhi;   // scratch for the new bands
+    hipLaunchKernelGGL(k_bands, dim3(L->ntiles), dim3(256), 0, L->stream, L->d_mom, L->geo, theta, bmin, bmax, nlo,
+                       nhi);
+    HIPCHK(hipGetLastError());
+    std::vector<int32_t> lo(L->ntiles), hi(L->ntiles);
+    HIPCHK(hipMemcpyAsync(lo.data(), nlo, 4 * L->ntiles, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipMemcpyAsync(hi.data(), nhi, 4 * L->ntiles, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    return lb_change_regions(L, lo.data(), hi.data());
+}
+
+lb_status lb_project(int32_t ns, int32_t eqs, int32_t nd, int32_t eqd, const double *f_src, const double *closure,
+                     double *f_dst, int64_t n, void *hip_stream) {
+    if (!f_src || !f_dst || n < 0) return fail(LB_EINVAL, "bad argument");
+    const lbk::KernelSet *k = find_any(ns, eqs, nd, eqd);
+    if (!k) return fail(LB_EUNSUPPORTED, "no projection kernel for this pair");
+    k->project(f_src, closure, f_dst, n, reinterpret_cast<hipStream_t>(hip_stream));
+    HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_set_timing(lb_lattice *L, int32_t enable) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    HIPCHK(hipStreamSynchronize(L->stream));
+    L->timing = enable != 0;
+    L->ev_used = 0;
+    L->ev_kind.clear();
+    return LB_OK;
+}
+
+lb_status lb_kernel_times(lb_lattice *L, double *ms_high, int64_t *n_high, double *ms_all, int64_t *n_all) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    HIPCHK(hipStreamSynchronize(L->stream));
+    double mh = 0, ma = 0;
+    int64_t nh = 0, na = 0;
+    for (size_t k = 0; k < L->ev_kind.size(); ++k) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, L->ev_pool[2 * k], L->ev_pool[2 * k + 1]));
+        ma += ms;
+        na++;
+        if (L->ev_kind[k]) {
+            mh += ms;
+            nh++;
+        }
+    }
+    if (ms_high) *ms_high = mh;
+    if (n_high) *n_high = nh;
+    if (ms_all) *ms_all = ma;
+    if (n_all) *n_all = na;
+    L->ev_used = 0;
+    L->ev_kind.clear();
+    return LB_OK;
+}
+
+}  // extern "C"

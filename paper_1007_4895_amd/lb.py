@@ -1,0 +1,273 @@
+"""ctypes binding of liblb.so (include/lb.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI.  PyTorch supplies the device workspace and the stream.
+The library must be built (``paper_1007_4895_amd.build``); loading fails
+loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblb.so")
+
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EUNSTABLE, LB_EUNSUPPORTED, LB_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STORE_F64, STORE_F32, STORE_BF16 = 0, 1, 2
+IFACE_HERMITE, IFACE_PAPER = 0, 1
+TAU_CONST, TAU_RHO = 0, 1
+XBC_PERIODIC, XBC_PRESSURE = 0, 1
+YBC_WALLS, YBC_PERIODIC = 0, 1
+
+STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "bf16": STORE_BF16}
+
+
+class LBError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lb status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("n_low", C.c_int32), ("n_high", C.c_int32),
+        ("eq_low", C.c_int32), ("eq_high", C.c_int32),
+        ("force_low", C.c_int32), ("force_high", C.c_int32),
+        ("tau_mode", C.c_int32), ("xbc", C.c_int32), ("ybc", C.c_int32),
+        ("iface", C.c_int32), ("storage", C.c_int32), ("tile_w", C.c_int32),
+        ("kn", C.c_double), ("rho_ref", C.c_double), ("cfl", C.c_double), ("dt", C.c_double),
+        ("gx", C.c_double), ("gy", C.c_double), ("u_wall", C.c_double * 4),
+        ("rho_in", C.c_double), ("rho_out", C.c_double),
+    ]
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_vp = C.c_void_p
+
+
+def lib():
+    """Load liblb.so (never builds: a missing library is an error)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run paper_1007_4895_amd.build")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "lb_last_error": (C.c_char_p, []),
+            "lb_params_default": (C.c_int, [C.POINTER(Params)]),
+            "lb_workspace_bytes": (C.c_size_t, [C.POINTER(Params)]),
+            "lb_create_lattice": (C.c_int, [C.POINTER(Params), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+            "lb_destroy_lattice": (None, [_vp]),
+            "lb_get_info": (C.c_int, [_vp, _dp, _dp, _ip]),
+            "lb_set_regions": (C.c_int, [_vp, _ip, _ip]),
+            "lb_get_regions": (C.c_int, [_vp, _ip, _ip]),
+            "lb_init_equilibrium": (C.c_int, [_vp, _dp, _dp, _dp]),
+            "lb_step": (C.c_int, [_vp, C.c_int64]),
+            "lb_moments": (C.c_int, [_vp, _dp, _dp, _dp, C.c_int32]),
+            "lb_conservation": (C.c_int, [_vp, _dp]),
+            "lb_get_populations": (C.c_int, [_vp, C.c_int32, _dp]),
+            "lb_set_populations": (C.c_int, [_vp, C.c_int32, _dp]),
+            "lb_state_bytes": (C.c_size_t, [_vp]),
+            "lb_get_state": (C.c_int, [_vp, _vp, C.c_size_t]),
+            "lb_set_state": (C.c_int, [_vp, _vp, C.c_size_t]),
+            "lb_step_count": (C.c_int64, [_vp]),
+            "lb_indicator": (C.c_int, [_vp, _dp, C.c_int32]),
+            "lb_update_regions": (C.c_int, [_vp, C.c_double, C.c_int32, C.c_int32]),
+            "lb_change_regions": (C.c_int, [_vp, _ip, _ip]),
+            "lb_project": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp, C.c_int64, _vp]),
+            "lb_set_timing": (C.c_int, [_vp, C.c_int32]),
+            "lb_kernel_times": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int64)]),
+            "lb_set_strip_rows": (C.c_int, [_vp, C.c_int32]),
+            "lb_region_counts": (C.c_int, [_vp, C.POINTER(C.c_int64)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != LB_OK:
+        raise LBError(status, lib().lb_last_error().decode())
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_params(nx, ny, *, kn, n_low=3, n_high=3, eq_low=2, eq_high=None, storage="f64",
+                iface=IFACE_HERMITE, tau_mode=TAU_CONST, xbc=XBC_PERIODIC, ybc=YBC_WALLS,
+                tile_w=0, rho_ref=1.0, cfl=0.5, dt=0.0, gx=0.0, gy=0.0,
+                u_wall=((0.0, 0.0), (0.0, 0.0)), rho_in=1.0, rho_out=1.0) -> Params:
+    p = Params()
+    _check(lib().lb_params_default(C.byref(p)))
+    p.nx, p.ny = nx, ny
+    p.n_low, p.n_high = n_low, n_high
+    p.eq_low = eq_low
+    p.eq_high = eq_low if eq_high is None else eq_high
+    p.force_low = p.force_high = 0
+    p.storage = STORAGE[storage] if isinstance(storage, str) else storage
+    p.iface, p.tau_mode, p.xbc, p.ybc, p.tile_w = iface, tau_mode, xbc, ybc, tile_w
+    p.kn, p.rho_ref, p.cfl, p.dt = kn, rho_ref, cfl, dt
+    p.gx, p.gy = gx, gy
+    for k, v in enumerate((u_wall[0][0], u_wall[0][1], u_wall[1][0], u_wall[1][1])):
+        p.u_wall[k] = v
+    p.rho_in, p.rho_out = rho_in, rho_out
+    return p
+
+
+class Lattice:
+    """A lattice living in a torch-allocated device workspace on the current
+    torch stream (or the stream given)."""
+
+    def __init__(self, params: Params, device="cuda:0", stream=None):
+        import torch
+
+        self.p = params
+        self.nx, self.ny, self.nrow = params.nx, params.ny, params.ny + 1
+        self.Q = (params.n_low ** 2, params.n_high ** 2)
+        nbytes = lib().lb_workspace_bytes(C.byref(params))
+        if nbytes == 0:
+            _check(LB_EINVAL)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        base = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _vp()
+        _check(lib().lb_create_lattice(C.byref(params), _vp(base), nbytes, _vp(self.stream.cuda_stream),
+                                       C.byref(h)))
+        self._h = h
+        dt, tau0, nt = C.c_double(), C.c_double(), C.c_int32()
+        _check(lib().lb_get_info(h, C.byref(dt), C.byref(tau0), C.byref(nt)))
+        self.dt, self.tau0, self.ntiles = dt.value, tau0.value, nt.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lb_destroy_lattice(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- regions
+    def _bands(self, lo, hi):
+        lo = np.ascontiguousarray(np.broadcast_to(np.asarray(lo, dtype=np.int32), (self.ntiles,)))
+        hi = np.ascontiguousarray(np.broadcast_to(np.asarray(hi, dtype=np.int32), (self.ntiles,)))
+        return lo, hi
+
+    def set_regions(self, lo, hi):
+        lo, hi = self._bands(lo, hi)
+        _check(lib().lb_set_regions(self._h, lo.ctypes.data_as(_ip), hi.ctypes.data_as(_ip)))
+
+    def change_regions(self, lo, hi):
+        lo, hi = self._bands(lo, hi)
+        _check(lib().lb_change_regions(self._h, lo.ctypes.data_as(_ip), hi.ctypes.data_as(_ip)))
+
+    def get_regions(self):
+        lo = np.zeros(self.ntiles, dtype=np.int32)
+        hi = np.zeros(self.ntiles, dtype=np.int32)
+        _check(lib().lb_get_regions(self._h, lo.ctypes.data_as(_ip), hi.ctypes.data_as(_ip)))
+        return lo, hi
+
+    def update_regions(self, theta, bmin, bmax):
+        _check(lib().lb_update_regions(self._h, theta, bmin, bmax))
+
+    def region_counts(self):
+        c = (C.c_int64 * 3)()
+        _check(lib().lb_region_counts(self._h, c))
+        return tuple(c)
+
+    def set_strip_rows(self, rows):
+        _check(lib().lb_set_strip_rows(self._h, rows))
+
+    # ----------------------------------------------------------------- state
+    def init_equilibrium(self, rho=None, ux=None, uy=None):
+        arrs = [None if a is None else _f64(np.broadcast_to(a, (self.nrow, self.nx))) for a in (rho, ux, uy)]
+        ptrs = [None if a is None else _d(a) for a in arrs]
+        _check(lib().lb_init_equilibrium(self._h, *ptrs))
+
+    def step(self, n=1):
+        _check(lib().lb_step(self._h, int(n)))
+
+    @property
+    def steps(self):
+        return lib().lb_step_count(self._h)
+
+    def moments(self):
+        shp = (self.nrow, self.nx)
+        r, ux, uy = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+        _check(lib().lb_moments(self._h, _d(r), _d(ux), _d(uy), 0))
+        return r, ux, uy
+
+    def moments_device(self, rho, ux, uy):
+        """Asynchronous moments into three float64 torch tensors on the device."""
+        _check(lib().lb_moments(self._h, C.cast(rho.data_ptr(), _dp), C.cast(ux.data_ptr(), _dp),
+                                C.cast(uy.data_ptr(), _dp), 1))
+
+    def conservation(self):
+        out = np.zeros(3)
+        _check(lib().lb_conservation(self._h, _d(out)))
+        return out
+
+    def get_populations(self, which):
+        f = np.zeros((self.Q[which], self.nrow, self.nx))
+        _check(lib().lb_get_populations(self._h, which, _d(f)))
+        return f
+
+    def set_populations(self, which, f):
+        f = _f64(f)
+        assert f.shape == (self.Q[which], self.nrow, self.nx)
+        _check(lib().lb_set_populations(self._h, which, _d(f)))
+
+    def get_state(self) -> bytes:
+        n = lib().lb_state_bytes(self._h)
+        buf = C.create_string_buffer(n)
+        _check(lib().lb_get_state(self._h, buf, n))
+        return buf.raw
+
+    def set_state(self, b: bytes):
+        buf = C.create_string_buffer(b, len(b))
+        _check(lib().lb_set_state(self._h, buf, len(b)))
+
+    def indicator(self):
+        B = np.zeros((self.nrow, self.nx))
+        _check(lib().lb_indicator(self._h, _d(B), 0))
+        return B
+
+    # ---------------------------------------------------------------- timing
+    def set_timing(self, on=True):
+        _check(lib().lb_set_timing(self._h, 1 if on else 0))
+
+    def kernel_times(self):
+        mh, ma = C.c_double(), C.c_double()
+        nh, na = C.c_int64(), C.c_int64()
+        _check(lib().lb_kernel_times(self._h, C.byref(mh), C.byref(nh), C.byref(ma), C.byref(na)))
+        return mh.value, nh.value, ma.value, na.value
+
+
+def project(ns, eqs, nd, eqd, f_src, f_dst, closure=None, stream=None):
+    """Hermite-moment projection of n nodes on the device: f_src [n, ns*ns],
+    f_dst [n, nd*nd], closure [n, nd*nd] or None (float64 torch tensors)."""
+    import torch
+
+    n = f_src.shape[0]
+    st = stream if stream is not None else torch.cuda.current_stream(f_src.device)
+    cl = None if closure is None else _vp(closure.data_ptr())
+    _check(lib().lb_project(ns, eqs, nd, eqd, _vp(f_src.data_ptr()), cl, _vp(f_dst.data_ptr()), n,
+                            _vp(st.cuda_stream)))

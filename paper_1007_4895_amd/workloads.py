@@ -1,0 +1,69 @@
+"""Seeded synthetic inputs and workload recipes.
+
+This module holds none of the method's arithmetic: it only draws seeded
+random numbers (smooth density/velocity fields, noise arrays) and states the
+sizes and parameters of the channel-flow workloads.  Both the GPU path and
+the CPU oracle are fed from here.
+
+Workloads (all synthetic: the paper's cases are analytic channel flows):
+  couette_c1   planar Couette, nx = 4 (periodic) x ny = 64, walls -/+0.05,
+               Kn = 0.1, D2Q16 (3rd-order equilibrium) in 8 rows at each
+               wall, D2Q9 core, Hermite interface, FP64, 20k steps.
+  poiseuille_c2  body-force channel nx = 1024 x ny = 512, g = 1e-6,
+               Kn in {0.01, 0.05, 0.1}, D2Q36 (4th order) in 64 rows at each
+               wall, D2Q9 elsewhere, FP32, 10k steps; all-D2Q36 comparison.
+  pressure_c3  pressure-driven channel nx = 4096 x ny = 256, rho_in/rho_out
+               = 2, outlet Kn = 0.2 (relaxation time ~ 1/rho), bands per
+               64-column tile from the non-equilibrium indicator every 500
+               steps, FP32 or BF16 storage.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+D2Q9, D2Q16, D2Q36 = 3, 4, 6   # Gauss-Hermite points per axis
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def smooth_fields(nx: int, nrow: int, seed: int, rho_amp=0.02, u_amp=0.03, modes=3,
+                  x_uniform=False):
+    """rho, ux, uy on [nrow][nx]: 1 + / 0 + a few random low-wavenumber
+    sinusoids (periodic in x; in y over nrow rows)."""
+    g = rng(seed)
+    y, x = np.mgrid[0:nrow, 0:nx].astype(np.float64)
+    out = []
+    for base, amp in ((1.0, rho_amp), (0.0, u_amp), (0.0, u_amp)):
+        f = np.full((nrow, nx), base)
+        for _ in range(modes):
+            kx = 0 if x_uniform else int(g.integers(0, 3))
+            ky = int(g.integers(1, 3))
+            ph = g.uniform(0, 2 * np.pi, 2)
+            a = amp * g.uniform(0.3, 1.0) / modes
+            f = f + a * np.cos(2 * np.pi * kx * x / nx + ph[0]) * np.sin(np.pi * ky * y / max(nrow - 1, 1) + ph[1])
+        out.append(f)
+    return out
+
+
+def noise(shape, seed: int, amp: float):
+    """Uniform noise in [-amp, amp]."""
+    return amp * rng(seed).uniform(-1.0, 1.0, shape)
+
+
+def tile_bands(ntiles: int, seed: int, lo: int, hi: int):
+    """Per-tile band widths, uniform integers in [lo, hi]."""
+    g = rng(seed)
+    return g.integers(lo, hi + 1, ntiles).astype(np.int32), g.integers(lo, hi + 1, ntiles).astype(np.int32)
+
+
+COUETTE_C1 = dict(nx=4, ny=64, kn=0.1, n_low=D2Q9, n_high=D2Q16, eq_low=2, eq_high=3,
+                  u_wall=((-0.05, 0.0), (0.05, 0.0)), bands=(8, 8), storage="f64", steps=20000)
+
+POISEUILLE_C2 = dict(nx=1024, ny=512, kn=0.05, kn_sweep=(0.01, 0.05, 0.1), n_low=D2Q9, n_high=D2Q36,
+                     eq_low=2, eq_high=4, gx=1e-6, bands=(64, 64), storage="f32", steps=10000)
+
+PRESSURE_C3 = dict(nx=4096, ny=256, kn=0.2, n_low=D2Q9, n_high=D2Q36, eq_low=2, eq_high=4,
+                   rho_in=2.0, rho_out=1.0, tile_w=64, theta=0.01, bmin=8, bmax=64, regrid=500,
+                   cfl=0.3, storage="f32", steps=20000)

@@ -1,0 +1,91 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/lb.h declares, its parameter struct has the layout the C compiler
+gives it, and parameter validation reports errors (no kernel runs)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lb.h")
+
+
+@pytest.fixture(scope="module")
+def lbmod():
+    from paper_1007_4895_amd import lb
+    if not os.path.exists(lb.LIB_PATH):
+        from paper_1007_4895_amd import build
+        build.build()
+    lb.lib()
+    return lb
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lbmod):
+    names = _declared()
+    assert len(names) >= 20
+    L = C.CDLL(lbmod.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_params_layout_matches_c(lbmod, tmp_path):
+    fields = [f for f, _ in lbmod.Params._fields_]
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void){',
+             'printf("%zu\\n", sizeof(lb_params));']
+    for f in fields:
+        lines.append(f'printf("%zu\\n", offsetof(lb_params, {f}));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert out[0] == C.sizeof(lbmod.Params)
+    for f, off in zip(fields, out[1:]):
+        assert getattr(lbmod.Params, f).offset == off, f
+
+
+def test_validation_errors(lbmod):
+    L = lbmod.lib()
+
+    def ws(**kw):
+        p = lbmod.make_params(**kw)
+        return L.lb_workspace_bytes(C.byref(p)), L.lb_last_error().decode()
+
+    n, _ = ws(nx=64, ny=64, kn=0.1)
+    assert n > 0
+    n, err = ws(nx=64, ny=64, kn=0.1, n_low=4, eq_low=4)        # order above degree rule
+    assert n == 0 and "order" in err
+    n, err = ws(nx=64, ny=64, kn=0.1, n_low=5)
+    assert n == 0 and "not built" in err
+    n, err = ws(nx=64, ny=64, kn=0.1, cfl=0.7)
+    assert n == 0 and "cfl" in err
+    n, err = ws(nx=64, ny=64, kn=0.001)                         # dt above tau
+    assert n == 0 and "relaxation" in err
+    n, err = ws(nx=100, ny=64, kn=0.1, tile_w=50)
+    assert n == 0 and "tile_w" in err
+    n, err = ws(nx=1, ny=64, kn=0.1)
+    assert n == 0
+
+
+def test_default_time_step_matches_gauss_hermite_rule(lbmod, oracle):
+    # dt = cfl / x_max of the fastest set; both sides compute x_max independently
+    import numpy as np
+    for n in (3, 4, 6):
+        x, _ = oracle.gh_rule(n)
+        want = 0.5 / float(np.max(x))
+        # the library reports its dt only for a created lattice; its x_max
+        # enters through the Courant check: dt = want passes, dt*(1+1e-9)/0.5 fails
+        L = lbmod.lib()
+        p = lbmod.make_params(nx=8, ny=64, kn=1.0, n_low=n, n_high=n, eq_low=2, dt=2 * want)
+        assert L.lb_workspace_bytes(C.byref(p)) > 0
+        p = lbmod.make_params(nx=8, ny=64, kn=1.0, n_low=n, n_high=n, eq_low=2, dt=2 * want * (1 + 1e-9))
+        assert L.lb_workspace_bytes(C.byref(p)) == 0

@@ -1,0 +1,323 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances: FP64 storage 1e-10 relative (rounding order, FMA contraction and
+the minmod form of the limiter differ from the oracle, nothing else); FP32
+(weight-shifted) storage 1e-5 relative velocity error.  Sizes span several
+64-column waves with a ragged tail, and the full channel sizes in the
+launch configuration of the benchmark.
+"""
+import numpy as np
+import pytest
+
+from paper_1007_4895_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1007_4895_amd import lb as m
+    m.lib()
+    return m
+
+
+def pair(oracle, lb, nx, ny, *, storage="f64", bands=(0, 0), strip=0, dt=None, **kw):
+    """Oracle and GPU lattices with identical parameters and dt."""
+    n_hi = max(kw.get("n_low", 3), kw.get("n_high", kw.get("n_low", 3)))
+    if dt is None:
+        cfl = kw.pop("cfl", 0.5)
+        x, _ = oracle.gh_rule(n_hi)
+        dt = cfl / float(np.max(x))
+    else:
+        kw.pop("cfl", None)
+    okw = dict(kw)
+    for k in ("tile_w",):
+        if okw.get(k, None) == 0:
+            okw.pop(k)
+    O = oracle.Lattice(nx, ny, dt=dt, **okw)
+    G = lb.Lattice(lb.make_params(nx, ny, storage=storage, dt=dt, **kw))
+    if strip:
+        G.set_strip_rows(strip)
+    O.set_regions(*bands)
+    G.set_regions(*bands)
+    return O, G
+
+
+def rel_u(ux_a, uy_a, ux_b, uy_b, mask=None):
+    if mask is None:
+        mask = np.ones(ux_a.shape, bool)
+    num = np.sqrt(np.sum((ux_a - ux_b)[mask] ** 2 + (uy_a - uy_b)[mask] ** 2))
+    den = np.sqrt(np.sum(ux_b[mask] ** 2 + uy_b[mask] ** 2))
+    return num / den
+
+
+def pop_err(G, O, which):
+    g, o = G.get_populations(which), O.get_populations(which)
+    m = ~np.isnan(g[0])
+    return np.max(np.abs(g[:, m] - o[:, m])) / np.max(np.abs(o[:, m])), m.sum()
+
+
+# ------------------------------------------------------------ single sets
+@pytest.mark.parametrize("n,N", [(3, 2), (4, 3), (6, 4)])
+def test_single_set_periodic_2d(oracle, lb, n, N):
+    # 150 columns = 2 full waves + a ragged 22-column tail; fully periodic
+    # 2D data (Courant 0.3); non-equilibrium start from seeded noise
+    nx, ny = 150, 19
+    O, G = pair(oracle, lb, nx, ny, n_low=n, n_high=n, eq_low=N, kn=0.2, gx=2e-4, gy=-1e-4,
+                ybc=oracle.YBC_PERIODIC, cfl=0.3)
+    rho, ux, uy = W.smooth_fields(nx, ny + 1, seed=11, rho_amp=0.05, u_amp=0.05)
+    O.init_equilibrium(rho, ux, uy)
+    f = O.get_populations(0) * (1 + W.noise((n * n, ny + 1, nx), seed=12, amp=0.01))
+    O.set_populations(0, f)
+    G.set_populations(0, f)
+    e0, cnt = pop_err(G, O, 0)
+    assert cnt == nx * (ny + 1) and e0 < 1e-15
+    for k in (1, 4, 25):
+        O.step(k)
+        G.step(k)
+        e, _ = pop_err(G, O, 0)
+        assert e < 1e-12, (k, e)
+    _, uxo, uyo = O.moments()
+    _, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-11
+
+
+@pytest.mark.parametrize("n,N", [(3, 2), (6, 4)])
+def test_single_set_walls_force(oracle, lb, n, N):
+    # moving diffuse walls, body force, 2D start; 70 columns (ragged wave)
+    nx, ny = 70, 24
+    O, G = pair(oracle, lb, nx, ny, n_low=n, n_high=n, eq_low=N, kn=0.1, gx=1e-4,
+                u_wall=((0.03, 0.0), (-0.02, 0.0)), cfl=0.3)
+    rho, ux, uy = W.smooth_fields(nx, ny + 1, seed=21)
+    O.init_equilibrium(rho, ux, uy)
+    G.init_equilibrium(rho, ux, uy)
+    O.step(60)
+    G.step(60)
+    e, _ = pop_err(G, O, 0)
+    assert e < 1e-11
+    r_o, uxo, uyo = O.moments()
+    r_g, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
+    assert np.max(np.abs(r_g - r_o)) < 1e-12
+
+
+# ---------------------------------------------------------------- coupled
+@pytest.mark.parametrize("lo,hi", [((3, 2), (4, 3)), ((3, 2), (6, 4)), ((4, 3), (6, 4))])
+def test_coupled_hermite_2d(oracle, lb, lo, hi):
+    nx, ny = 130, 40
+    O, G = pair(oracle, lb, nx, ny, n_low=lo[0], eq_low=lo[1], n_high=hi[0], eq_high=hi[1], kn=0.08,
+                gx=5e-5, u_wall=((-0.03, 0.0), (0.03, 0.0)), bands=(7, 9), cfl=0.3)
+    rho, ux, uy = W.smooth_fields(nx, ny + 1, seed=31)
+    O.init_equilibrium(rho, ux, uy)
+    G.init_equilibrium(rho, ux, uy)
+    for k in (1, 30):
+        O.step(k)
+        G.step(k)
+        for s in (0, 1):
+            e, _ = pop_err(G, O, s)
+            assert e < 1e-11, (k, s, e)
+    r_o, uxo, uyo = O.moments()
+    r_g, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
+
+
+def test_couette_c1_full_run(oracle, lb):
+    c = W.COUETTE_C1
+    O, G = pair(oracle, lb, c["nx"], c["ny"], n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"],
+                eq_high=c["eq_high"], kn=c["kn"], u_wall=c["u_wall"], bands=c["bands"])
+    O.init_equilibrium()
+    G.init_equilibrium()
+    O.step(c["steps"])
+    G.step(c["steps"])
+    r_o, uxo, uyo = O.moments()
+    r_g, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
+    assert np.max(np.abs(r_g - r_o)) < 1e-12
+    # steady profile is antisymmetric on the GPU too
+    assert np.max(np.abs(uxg[:, 0] + uxg[::-1, 0])) < 1e-12
+
+
+def test_paper_interface(oracle, lb):
+    nx, ny = 70, 40
+    O, G = pair(oracle, lb, nx, ny, n_low=3, eq_low=2, n_high=6, eq_high=2, kn=0.1,
+                iface=oracle.IFACE_PAPER, u_wall=((-0.04, 0.0), (0.04, 0.0)), bands=(6, 8), cfl=0.3)
+    rho, ux, uy = W.smooth_fields(nx, ny + 1, seed=41)
+    O.init_equilibrium(rho, ux, uy)
+    G.init_equilibrium(rho, ux, uy)
+    O.step(50)
+    G.step(50)
+    for s in (0, 1):
+        e, _ = pop_err(G, O, s)
+        assert e < 1e-11
+    r_o, uxo, uyo = O.moments()
+    r_g, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
+
+
+def test_pressure_channel_tile_bands(oracle, lb):
+    # pressure x-boundary, relaxation time ~ 1/rho, per-tile bands (64-column
+    # tiles, differing widths -> x-neighbours across tiles in the other set)
+    nx, ny = 256, 40
+    lo, hi = W.tile_bands(4, seed=51, lo=3, hi=9)
+    O, G = pair(oracle, lb, nx, ny, n_low=3, eq_low=2, n_high=6, eq_high=4, kn=0.2,
+                xbc=oracle.XBC_PRESSURE, rho_in=1.2, rho_out=1.0, tau_mode=oracle.TAU_RHO,
+                tile_w=64, bands=(lo, hi), cfl=0.3)
+    x = np.arange(nx)[None, :] * np.ones((ny + 1, 1))
+    rho = 1.2 - 0.2 * x / (nx - 1)
+    O.init_equilibrium(rho, 0 * x, 0 * x)
+    G.init_equilibrium(rho, 0 * x, 0 * x)
+    O.step(40)
+    G.step(40)
+    for s in (0, 1):
+        e, _ = pop_err(G, O, s)
+        assert e < 1e-11, (s, e)
+    r_o, uxo, uyo = O.moments()
+    r_g, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
+
+
+# ---------------------------------------------------------------- storage
+def test_fp32_coupled_channel(oracle, lb):
+    nx, ny = 130, 64
+    O, G = pair(oracle, lb, nx, ny, storage="f32", n_low=3, eq_low=2, n_high=6, eq_high=4, kn=0.05,
+                gx=1e-5, u_wall=((-0.02, 0.0), (0.02, 0.0)), bands=(8, 8), cfl=0.3)
+    rho, ux, uy = W.smooth_fields(nx, ny + 1, seed=61, rho_amp=0.01, u_amp=0.01)
+    O.init_equilibrium(rho, ux, uy)
+    G.init_equilibrium(rho, ux, uy)
+    O.step(300)
+    G.step(300)
+    _, uxo, uyo = O.moments()
+    _, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-5
+
+
+def test_poiseuille_c2_full_width_x_uniform(oracle, lb):
+    # the benchmark workload at full size (1024 x 513, D2Q36 in 64 rows at each
+    # wall, FP32): the flow stays bit-for-bit x-uniform, so every column is
+    # checked against the oracle run at nx = 4
+    c = W.POISEUILLE_C2
+    steps = 2000
+    x, _ = oracle.gh_rule(6)
+    dt = 0.5 / float(np.max(x))
+    kw = dict(n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"], eq_high=c["eq_high"], kn=c["kn"],
+              gx=c["gx"])
+    G = lb.Lattice(lb.make_params(c["nx"], c["ny"], storage=c["storage"], dt=dt, **kw))
+    G.set_regions(*c["bands"])
+    G.init_equilibrium()
+    G.step(steps)
+    r_g, uxg, uyg = G.moments()
+    assert np.all(uxg == uxg[:, :1]) and np.all(r_g == r_g[:, :1])
+    O = oracle.Lattice(4, c["ny"], dt=dt, **kw)
+    O.set_regions(*c["bands"])
+    O.init_equilibrium()
+    O.step(steps)
+    r_o, uxo, uyo = O.moments()
+    assert rel_u(uxg[:, :4], uyg[:, :4], uxo, uyo) < 1e-5
+
+
+# ------------------------------------------------------- runtime properties
+def test_strip_rows_invariance_and_determinism(lb):
+    def run(strip):
+        G = lb.Lattice(lb.make_params(200, 60, kn=0.1, n_low=3, n_high=6, eq_low=2, eq_high=4, storage="f32",
+                                      gx=1e-5, cfl=0.3, u_wall=((0.01, 0.0), (-0.01, 0.0))))
+        G.set_regions(10, 12)
+        if strip:
+            G.set_strip_rows(strip)
+        rho, ux, uy = W.smooth_fields(200, 61, seed=71)
+        G.init_equilibrium(rho, ux, uy)
+        G.step(50)
+        return G.get_populations(0), G.get_populations(1)
+
+    a = run(0)
+    for strip in (1, 5, 64):
+        b = run(strip)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_checkpoint_resume_bitwise(lb):
+    def make():
+        G = lb.Lattice(lb.make_params(96, 40, kn=0.1, n_low=3, n_high=4, eq_low=2, eq_high=3, storage="f32",
+                                      gx=1e-5, u_wall=((0.02, 0.0), (-0.02, 0.0))))
+        G.set_regions(6, 6)
+        G.init_equilibrium()
+        return G
+
+    A = make()
+    A.step(300)
+    B = make()
+    B.step(150)
+    st = B.get_state()
+    C = make()
+    C.set_state(st)
+    assert C.steps == 150
+    C.step(150)
+    for s in (0, 1):
+        np.testing.assert_array_equal(A.get_populations(s), C.get_populations(s))
+
+
+def test_conservation_periodic(lb):
+    nx, ny = 128, 31
+    G = lb.Lattice(lb.make_params(nx, ny, kn=0.2, n_low=4, n_high=4, eq_low=3, gx=1e-4,
+                                  ybc=lb.YBC_PERIODIC, cfl=0.3))
+    rho, ux, uy = W.smooth_fields(nx, ny + 1, seed=81)
+    G.init_equilibrium(rho, ux, uy)
+    c0 = G.conservation()
+    G.step(200)
+    c1 = G.conservation()
+    assert abs(c1[0] - c0[0]) / c0[0] < 1e-13
+    assert abs((c1[1] - c0[1]) - 200 * G.dt * 1e-4 * c0[0]) < 1e-11
+
+
+def test_projection_kernel(oracle, lb):
+    import torch
+    rng = np.random.default_rng(91)
+    for (ns, es), (nd, ed) in (((3, 2), (6, 4)), ((6, 4), (3, 2)), ((4, 3), (6, 4)), ((6, 4), (4, 3))):
+        n = 37
+        f = np.stack([oracle.equilibrium(ns, es, 1 + 0.05 * rng.uniform(), 0.05 * rng.uniform(-1, 1),
+                                         0.05 * rng.uniform(-1, 1)) for _ in range(n)])
+        f = f * (1 + 0.01 * rng.uniform(-1, 1, f.shape))
+        src = torch.tensor(f, device="cuda", dtype=torch.float64)
+        dst = torch.zeros((n, nd * nd), device="cuda", dtype=torch.float64)
+        lb.project(ns, es, nd, ed, src, dst)
+        torch.cuda.synchronize()
+        got = dst.cpu().numpy()
+        want = np.stack([oracle.project(ns, es, nd, ed, f[k]) for k in range(n)])
+        assert np.max(np.abs(got - want)) < 1e-15
+
+
+def test_region_change_and_indicator(oracle, lb):
+    nx, ny = 128, 48
+    O, G = pair(oracle, lb, nx, ny, n_low=3, eq_low=2, n_high=6, eq_high=4, kn=0.1, tile_w=64,
+                u_wall=((-0.05, 0.0), (0.05, 0.0)), bands=(6, 6), cfl=0.3)
+    O.init_equilibrium()
+    G.init_equilibrium()
+    O.step(100)
+    G.step(100)
+    lo, hi = np.array([10, 4], np.int32), np.array([5, 12], np.int32)
+    O.update_regions(lo, hi)
+    G.change_regions(lo, hi)
+    for s in (0, 1):
+        e, _ = pop_err(G, O, s)
+        assert e < 1e-12
+    O.step(20)
+    G.step(20)
+    r_o, uxo, uyo = O.moments()
+    r_g, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
+    Bo, Bg = O.indicator(), G.indicator()
+    assert np.max(np.abs(Bg - Bo)) < 1e-12 * max(1.0, np.max(Bo))
+    # bands from the indicator: bit-exact away from the threshold
+    Bs = np.unique(Bo)
+    k = int(0.7 * len(Bs))
+    theta = float(0.5 * (Bs[k] + Bs[k + 1]))
+    bo = O.bands_from_indicator(Bo, theta, 2, 20)
+    G.update_regions(theta, 2, 20)
+    bg = G.get_regions()
+    guard = np.abs(Bo - theta) <= 1e-9 * theta
+    assert guard.sum() == 0
+    np.testing.assert_array_equal(bg[0], bo[0])
+    np.testing.assert_array_equal(bg[1], bo[1])
