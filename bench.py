@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark: coupled D2Q9/D2Q36 lattice Boltzmann channel on one MI355X.
+
+Workload (synthetic, the paper's cases are analytic channel flows): body-force
+Poiseuille channel 1024 x 513 nodes, g = 1e-6, Kn = 0.05, D2Q36 with a
+4th-order equilibrium in 64 rows at each wall, D2Q9 (2nd order) elsewhere,
+Hermite-moment interface, FP32 weight-shifted populations.  One step = one
+full time step of the hot path (update kernels of both sets + the finish
+pass: walls, images, interface projections).
+
+Prints one JSON line: coupled MLUPS (value), the all-D2Q36 MLUPS of the same
+case, algorithmic HBM GB/s, the roofline of the dominant kernel (D2Q36
+update), the model error of the coupled run against all-D2Q36 per Kn, and
+the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2q36_update_poiseuille_c2.json")
+KERNEL_SOURCES = ["lb_kernels.hpp", "lb_tables.hpp", "lb_internal.hpp", "lb_inst.hpp", "lb_inst_f32.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1007_4895_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make(lb, W, kn, all_high, bands=None):
+    c = W.POISEUILLE_C2
+    p = lb.make_params(c["nx"], c["ny"], kn=kn, n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"],
+                       eq_high=c["eq_high"], gx=c["gx"], storage=c["storage"])
+    L = lb.Lattice(p)
+    if all_high:
+        L.set_regions(c["ny"] + 1, 0)
+    else:
+        L.set_regions(*(bands or c["bands"]))
+    L.init_equilibrium()
+    return L
+
+
+def timed(L, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.step(steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--quick", action="store_true", help="coupled timed region only (for profiler runs)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the strip autotuner")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="also run N launches of a plain 256 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1007_4895_amd import lb, workloads as W
+
+    c = W.POISEUILLE_C2
+    nodes = c["nx"] * (c["ny"] + 1)
+    torch.cuda.init()
+
+    if args.copy_calib:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(args.copy_calib):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {args.copy_calib} x {src.numel() * 4} bytes read + written", flush=True)
+
+    # ---------------------------------------------------- coupled, timed
+    Lc = make(lb, W, c["kn"], all_high=False)
+    counts = Lc.region_counts()
+    strips = Lc.strip_rows() if args.no_tune else Lc.autotune(100)
+    Lc.step(args.warmup)
+    sec = timed(Lc, args.steps, torch)
+    cons = Lc.conservation()
+    mlups = nodes * args.steps / sec / 1e6
+    alg_bytes_step = 4 * 2 * (counts[0] * 9 + counts[1] * 36)
+    print(f"coupled: {args.steps} steps in {sec:.4f} s, {mlups:.1f} MLUPS", flush=True)
+
+    # roofline of the dominant kernel (the D2Q36 update): HIP events around
+    # every launch on the lattice stream over a timed region
+    nprof = min(args.steps, 2000)
+    Lc.set_timing(True)
+    Lc.step(nprof)
+    ms_h, n_h, ms_all, n_all = Lc.kernel_times()
+    Lc.set_timing(False)
+    avg_ms = ms_h / max(n_h, 1)
+    dom_bytes = 4 * 2 * 36 * counts[1]
+    achieved = dom_bytes / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("kernel_hash") == kernel_hash():
+            traffic = t.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_update<F32, D2Q36 order 4>", "bytes_per_launch": dom_bytes,
+                "avg_launch_ms": round(avg_ms, 5), "launches": n_h, "timing": "hipExtLaunchKernelGGL events"}
+    out = {
+        "metric": "coupled-LB MLUPS (D2Q9 core + D2Q36 near-wall bands) vs all-D2Q36",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * sec / args.steps, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "poiseuille_c2: 1024x513 body-force channel, g=1e-6, Kn=0.05, D2Q36 (order 4) "
+                               "in 64 rows at each wall, D2Q9 core, Hermite interface, FP32 weight-shifted "
+                               "populations", "nodes": nodes, "d2q36_nodes": counts[1], "d2q9_nodes": counts[0]},
+        "hbm_gbs_algorithmic": round(alg_bytes_step * args.steps / sec / 1e9, 1),
+        "strip_rows": {"d2q9": strips[0], "d2q36": strips[1]},
+        "roofline": roofline,
+        "conservation_finite": bool(np.all(np.isfinite(cons))),
+    }
+    if args.quick:
+        print(json.dumps(out))
+        return
+
+    # ----------------------------------------------- all-D2Q36 comparison
+    La = make(lb, W, c["kn"], all_high=True)
+    sa = La.strip_rows() if args.no_tune else La.autotune(100)
+    La.step(args.warmup)
+    sec_a = timed(La, args.steps, torch)
+    mlups_a = nodes * args.steps / sec_a / 1e6
+    out["all_d2q36_mlups"] = round(mlups_a, 1)
+    out["speedup_vs_all_d2q36"] = round(mlups / mlups_a, 3)
+    out["all_d2q36_hbm_gbs_algorithmic"] = round(4 * 2 * 36 * nodes * args.steps / sec_a / 1e9, 1)
+    del La
+    print(f"all-D2Q36: {mlups_a:.1f} MLUPS", flush=True)
+
+    # ---------- model error of the coupled run vs all-D2Q36, per Kn and band
+    # (the full 10k-step run from rest of the workload; velocity field of the
+    # whole lattice, relative L2 error)
+    def velocity(L):
+        _, ux, uy = L.moments()
+        return ux, uy
+
+    emodel, gated = {}, {}
+    for kn in c["kn_sweep"]:
+        La = make(lb, W, kn, all_high=True)
+        La.step(c["steps"])
+        ua = velocity(La)
+        del La
+        row = {}
+        for b in (64, 96, 128, 160, 192, 256):
+            L = make(lb, W, kn, all_high=False, bands=(b, b))
+            L.step(c["steps"])
+            uc = velocity(L)
+            del L
+            e = float(np.sqrt(np.sum((uc[0] - ua[0]) ** 2 + (uc[1] - ua[1]) ** 2) /
+                              np.sum(ua[0] ** 2 + ua[1] ** 2)))
+            row[str(b)] = e
+            if e <= 1e-3 and str(kn) not in gated:
+                gated[str(kn)] = {"band_rows": b, "e_model": e}
+        emodel[str(kn)] = row
+        print(f"E_model Kn={kn}: {row}", flush=True)
+    # speed of the narrowest band meeting the 1e-3 gate, per Kn
+    for kn, g in gated.items():
+        L = make(lb, W, float(kn), all_high=False, bands=(g["band_rows"], g["band_rows"]))
+        if not args.no_tune:
+            L.autotune(50)
+        L.step(args.warmup)
+        sec_g = timed(L, args.steps, torch)
+        g["mlups"] = round(nodes * args.steps / sec_g / 1e6, 1)
+        g["speedup_vs_all_d2q36"] = round(g["mlups"] / mlups_a, 3)
+        del L
+    out["e_model_vs_all_d2q36"] = emodel
+    out["e_model_steps"] = c["steps"]
+    out["gate_1e-3"] = gated
+
+    # ------------------------------- FP64 CPU oracle on a bounded sample
+    if not args.no_cpu:
+        import oracle
+        x, _ = oracle.gh_rule(6)
+        O = oracle.Lattice(c["nx"], c["ny"], kn=c["kn"], n_low=3, eq_low=2, n_high=6, eq_high=4, gx=c["gx"],
+                           dt=0.5 / float(np.max(x)))
+        O.set_regions(*c["bands"])
+        O.init_equilibrium()
+        ns = 10
+        t0 = time.perf_counter()
+        O.step(ns)
+        cs = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(nodes * ns / cs / 1e6, 4), "unit": "MLUPS", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{ns} steps of the same 1024x513 coupled case, FP64, 1 thread"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -163,8 +163,8 @@ lb_status lb_change_regions(lb_lattice *L, const int32_t *band_lo, const int32_t
 lb_status lb_project(int32_t ns, int32_t eqs, int32_t nd, int32_t eqd, const double *f_src,
                      const double *closure, double *f_dst, int64_t n, void *hip_stream);
 
-/* Kernel timing: when enabled, every update-kernel launch is bracketed by
- * HIP events on the lattice stream; lb_kernel_times returns, for the
+/* Kernel timing: when enabled, every update-kernel launch records start and
+ * stop HIP events (hipExtLaunchKernelGGL) on the lattice stream; lb_kernel_times returns, for the
  * dominant update kernel (the set that moves the most bytes per step) and
  * for all update kernels, the summed duration in ms and the launch count,
  * then clears them.  Waits. */
@@ -175,6 +175,16 @@ lb_status lb_kernel_times(lb_lattice *L, double *ms_high, int64_t *n_high, doubl
 /* Rows per work item of the update kernels (tuning; 0 = automatic: enough
  * items to fill the GPU, at most 16 rows). */
 lb_status lb_set_strip_rows(lb_lattice *L, int32_t rows);
+
+/* Current rows per work item of the low and high set's update kernel. */
+lb_status lb_get_strip_rows(const lb_lattice *L, int32_t rows[2]);
+
+/* Project-written autotuner: for each set, time the update kernel (kernel
+ * events over `steps` steps) for each candidate strip height and item order
+ * (per-XCD column slabs walked row-major, or column-major) and keep the
+ * fastest; the lattice state is saved before and restored after, so the
+ * physics is not advanced.  rows_out (may be NULL) receives the choice. */
+lb_status lb_autotune(lb_lattice *L, int32_t steps, int32_t rows_out[2]);
 
 /* Number of nodes in each region: [0] low set, [1] high set, [2] interface
  * rows (interpolation mode only). */

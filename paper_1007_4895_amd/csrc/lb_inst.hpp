@@ -3,16 +3,24 @@
 #include "lb_kernels.hpp"
 #include "lb_registry.hpp"
 
+#include <hip/hip_ext.h>
+
 namespace lbk {
 
 template <class ST, class S, class O>
 struct Inst {
     static int nodes_grid(const NodeArgs &a) { return (a.g.nrow * a.g.nx + 255) / 256; }
     static void update(const StepArgs &a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_update<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
+        hipLaunchKernelGGL((k_update<ST, S, O>), dim3(grid), dim3(64 * update_split<S>()), 0, s, a);
+    }
+    static void update_timed(const StepArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+        hipExtLaunchKernelGGL((k_update<ST, S, O>), dim3(grid), dim3(64 * update_split<S>()), 0, s, e0, e1, 0, a);
     }
     static void finish(const StepArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_finish<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
+    }
+    static void project_halo(const StepArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_project_halo<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
     }
     static void refresh(const NodeArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_refresh<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
@@ -50,7 +58,9 @@ struct Inst {
         k.nO = O::N;
         k.eqO = O::EQ;
         k.update = &update;
+        k.update_timed = &update_timed;
         k.finish = &finish;
+        k.project_halo = &project_halo;
         k.refresh = &refresh;
         k.init_eq = &init_eq;
         k.set_pop = &set_pop;

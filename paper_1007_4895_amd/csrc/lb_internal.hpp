@@ -50,6 +50,10 @@ struct Phys {
 struct SetK {
     double nu[8], kk[8];
     float nuf[8], kkf[8];
+    // diffuse walls [bottom, top]: S' = f_eq(1, u_wall) - w per population,
+    // K = sum_leaving |xi_y| w, D' = sum_leaving |xi_y| S'
+    double sp[2][36], wK[2], wD[2];
+    float spf[2][36], wKf[2], wDf[2];
 };
 
 struct StepArgs {

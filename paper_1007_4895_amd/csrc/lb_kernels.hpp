@@ -396,31 +396,104 @@ __device__ void finish_node(const Buf &self, const Buf &other, int copy, int i, 
 }
 
 // ------------------------------------------------------------- hot kernel
-// One time step of set SS.  Work item = 64 columns [i0, i0+64) x rows
-// [j0, j1), all evolved in SS.  Reads copy `cur`, writes copy `cur ^ 1`.
-template <class ST, class SS, class OO>
-__global__ __launch_bounds__(64) void k_update(const StepArgs A) {
-    using T = typename ST::M;
-    using SV = typename ST::S;
-    using TB = typename SS::T;
-    constexpr int N = SS::N, Q = SS::Q, EQ = SS::EQ;
+// One time step of set SS.  A work item is a group of 60 columns
+// [i0, i0+60) x a strip of rows [j0, j1).  The block has SPLIT waves; every
+// wave holds the same 64 columns [i0-2, i0+62) (the two extra columns on each
+// side are halo lanes that load but never store) and evolves the
+// populations of N/SPLIT of the set's y-abscissae, so per row a wave issues
+// one load and one store per population it owns -- well inside the 63
+// outstanding vector-memory operations a wave can track -- and needs about a
+// hundred registers.  The partial moments are exchanged through LDS (one
+// barrier per row) and summed in a fixed order, so every wave of the block
+// sees bit-identical rho and u.
+//
+// Loads are software-pipelined: as soon as a population's value for the
+// current row has been consumed, the load of its next-row value is issued,
+// so a whole row of arithmetic covers the memory latency.  Each lane marches
+// up its column keeping, per population, the values and limited slopes the
+// y fluxes need; x neighbours come from neighbouring lanes by DPP wave
+// shifts.
+//
+// Diffuse walls (Sec. 3.2) are applied on wall rows inside the kernel (a
+// wall row is the same for the whole block): the flux into the wall,
+// n = sum |xi_y| f over the populations moving into the wall, is reduced over
+// the block; the populations leaving the wall are then rho_W S(u_wall) with
+// rho_W = n / sum_leaving |xi_y| S.  With the storage shift s (stored
+// f' = f - w s) and S = w + S', this becomes f' = d w + (d + s) S' with
+// d = (n' - s D') / (K + D'), K = sum_leaving |xi_y| w,
+// D' = sum_leaving |xi_y| S' and n' the flux of the stored values, so no
+// large quantities cancel in FP32.
+template <class SS>
+constexpr int update_split() { return SS::Q == 36 ? 3 : SS::Q == 16 ? 2 : 1; }
 
+template <class T, int SPLIT>
+__device__ __forceinline__ T (*lds_moments())[3][SPLIT][64] {
+    __shared__ T sm[2][3][SPLIT][64];
+    return sm;
+}
+template <class T, int SPLIT>
+__device__ __forceinline__ T (*lds_wall())[SPLIT][64] {
+    __shared__ T sn[2][SPLIT][64];
+    return sn;
+}
+
+// occupancy the compiler must fit the update kernel into (waves per SIMD)
+template <class SS>
+constexpr int update_waves() { return SS::Q == 36 ? 4 : SS::Q == 16 ? 4 : 6; }
+
+template <class ST, class SS, class OO, int WV>
+__device__ __forceinline__ void update_rows(const StepArgs &A, const int i0, const int j0, const int j1,
+                                            const int lane);
+
+template <class ST, class SS, class OO>
+__global__ __launch_bounds__(64 * update_split<SS>())
+__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : update_waves<SS>())))
+void k_update(const StepArgs A) {
+    constexpr int SPLIT = update_split<SS>();
     // XCD-aware mapping: consecutive items (neighbouring strips) go to
     // blocks that the dispatcher places on the same XCD (block b -> XCD b % 8)
     const int b = blockIdx.x;
     const int it = (b & 7) * A.chunk + (b >> 3);
     if (it >= A.nitems) return;
     const int i0 = A.items[4 * it], j0 = A.items[4 * it + 1], j1 = A.items[4 * it + 2];
+    if (j0 >= j1) return;   // padding item
+    const int lane = threadIdx.x & 63;
+    // the wave index is wave-uniform: each wave runs the row loop compiled
+    // for its own abscissae, so every population's upwind direction and
+    // constants are known at compile time
+    const int wv = SPLIT > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6) : 0;
+    if (wv == 0) update_rows<ST, SS, OO, 0>(A, i0, j0, j1, lane);
+    if constexpr (SPLIT > 1) {
+        if (wv == 1) update_rows<ST, SS, OO, 1>(A, i0, j0, j1, lane);
+    }
+    if constexpr (SPLIT > 2) {
+        if (wv == 2) update_rows<ST, SS, OO, 2>(A, i0, j0, j1, lane);
+    }
+}
+
+template <class ST, class SS, class OO, int WV>
+__device__ __forceinline__ void update_rows(const StepArgs &A, const int i0, const int j0, const int j1,
+                                            const int lane) {
+    using T = typename ST::M;
+    using SV = typename ST::S;
+    using TB = typename SS::T;
+    constexpr int N = SS::N, Q = SS::Q, EQ = SS::EQ;
+    constexpr int SPLIT = update_split<SS>();
+    constexpr int NQ = N / SPLIT;      // y-abscissae per wave
+    constexpr int QW = NQ * N;         // populations per wave
+    constexpr int q0 = WV * NQ;
+    constexpr int wv = WV;
+    static_assert(N % SPLIT == 0, "split must divide the abscissae");
     const Geo &g = A.g;
-    const int lane = threadIdx.x;
     const int nx = g.nx;
-    const int i = i0 + lane;
-    const bool valid = i < nx;
+    const int col = i0 - 2 + lane;
+    const bool valid = lane >= 2 && lane < 62 && col < nx;
+
     // Addressing: raw buffer access with one descriptor per copy, the lane's
     // 32-bit byte offset (counted from column -2) in a vector register and
     // the wave-uniform offset of (population, row) in a scalar register.
-    // Lanes that must not load or store get an offset past the end of the
-    // buffer, which the hardware turns into a zero load / dropped store.
+    // Lanes that must not store get an offset past the end of the buffer,
+    // which the hardware turns into a dropped store (or a zero load).
     constexpr unsigned EB = sizeof(SV);
     const int64_t P = A.self.plane;
     const int64_t pitch = A.self.pitch;
@@ -431,16 +504,13 @@ __global__ __launch_bounds__(64) void k_update(const StepArgs A) {
     const __amdgpu_buffer_rsrc_t rd =
         __builtin_amdgcn_make_buffer_rsrc((void *)A.self.base[A.cur ^ 1], 0, int(nbytes), 0x00020000);
     const unsigned OOB = nbytes;
-    const unsigned vl = unsigned((i < nx + 1 ? i : nx + 1) + 2) * EB;
-    // halo columns: lane 0 <- i0-1, lane 1 <- i0-2, lane 62 <- i0+65, lane 63 <- i0+64
-    int ih;
-    if (lane == 0) ih = i0 - 1;
-    else if (lane == 1) ih = i0 - 2;
-    else if (lane == 62) ih = min(i0 + 65, nx + 1);
-    else ih = min(i0 + 64, nx + 1);
-    const unsigned vh = (lane < 2 || lane >= 62) ? unsigned(ih + 2) * EB : OOB;
-    const unsigned vs = valid ? unsigned(i + 2) * EB : OOB;
+    const unsigned vl = unsigned(min(max(col, -2), nx + 1) + 2) * EB;
 #define LB_SOFF(a, j) unsigned(((int64_t)(a) * P + rb + (int64_t)((j) + 2) * pitch) * EB)
+
+    // region ownership of this lane's column (bands of its tile)
+    const int tl = tile_of(min(max(col, 0), nx - 1), g);
+    const int lo_l = g.blo[tl], hi_l = g.bhi[tl];
+    const int want = A.self_high ? REG_HIGH : REG_LOW;
 
     // per-abscissa constants nu_p = x_p dt and k_p = |nu_p|(1 - |nu_p|)/2
     T nu[N], kk[N];
@@ -455,71 +525,101 @@ __global__ __launch_bounds__(64) void k_update(const StepArgs A) {
         }
     }
 
+    // wave-local population index a = p + N * (q0 + qq), qq < NQ
+#define LB_POP(k) ((k) % N + N * (q0 + (k) / N))
+    // first row's next-row values, issued together with the window
+    T nw[QW];
+#pragma unroll
+    for (int k = 0; k < QW; ++k) {
+        const double xq = TB::rule.x[q0 + k / N];
+        nw[k] = ST::bld(rs, vl, LB_SOFF(LB_POP(k), xq < 0.0 ? j0 + 2 : j0 + 1));
+    }
     // y window per population: c = f_j; for xi_y > 0: s1 = f_j - f_{j-1},
     // s2 = minmod(f_{j-1} - f_{j-2}, f_j - f_{j-1}); for xi_y < 0:
     // s1 = f_{j+1}, s2 = minmod(f_{j+1} - f_j, f_j - f_{j-1})
-    T c[Q], s1[Q], s2[Q];
+    T c[QW], s1[QW], s2[QW];
 #pragma unroll
-    for (int a = 0; a < Q; ++a) {
-        const double xq = TB::rule.x[a / N];
+    for (int k = 0; k < QW; ++k) {
+        const int a = LB_POP(k);
+        const double xq = TB::rule.x[q0 + k / N];
         if (xq > 0.0) {
             T fm2 = ST::bld(rs, vl, LB_SOFF(a, j0 - 2));
             T fm1 = ST::bld(rs, vl, LB_SOFF(a, j0 - 1));
             T f0 = ST::bld(rs, vl, LB_SOFF(a, j0));
-            c[a] = f0;
-            s1[a] = f0 - fm1;
-            s2[a] = minmod(fm1 - fm2, f0 - fm1);
+            c[k] = f0;
+            s1[k] = f0 - fm1;
+            s2[k] = minmod(fm1 - fm2, f0 - fm1);
         } else if (xq < 0.0) {
             T fm1 = ST::bld(rs, vl, LB_SOFF(a, j0 - 1));
             T f0 = ST::bld(rs, vl, LB_SOFF(a, j0));
             T fp1 = ST::bld(rs, vl, LB_SOFF(a, j0 + 1));
-            c[a] = f0;
-            s1[a] = fp1;
-            s2[a] = minmod(fp1 - f0, f0 - fm1);
+            c[k] = f0;
+            s1[k] = fp1;
+            s2[k] = minmod(fp1 - f0, f0 - fm1);
         } else {
-            c[a] = ST::bld(rs, vl, LB_SOFF(a, j0));
-            s1[a] = T(0);
-            s2[a] = T(0);
+            c[k] = ST::bld(rs, vl, LB_SOFF(a, j0));
+            s1[k] = T(0);
+            s2[k] = T(0);
         }
     }
 
-    // periodic images of the first/last two columns are written here; wall
-    // rows, row images, pressure columns and partner-set projections are
-    // finished afterwards by k_finish
+    // periodic images of the first/last two columns are written here; row
+    // images, pressure columns and partner-set projections are finished
+    // afterwards by k_finish / k_project_halo
     const bool per_x = g.xbc == XBC_PERIODIC;
-    const bool wave_img = per_x && (i0 < 2 || i0 + 64 > nx - 2);   // uniform
-    const unsigned vimg_lo = (per_x && valid && i < 2) ? unsigned(i + nx + 2) * EB : OOB;
-    const unsigned vimg_hi = (per_x && valid && i >= nx - 2) ? unsigned(i - nx + 2) * EB : OOB;
+    const bool wave_img = per_x && (i0 < 2 || i0 + 60 > nx - 2);   // uniform
 
     const T rho_shift = T(A.rho_shift);
     const T om0 = T(A.ph.omega0);
     const T om_rho = T(A.ph.omega0 / A.ph.rho_ref);
     const T dtT = T(A.ph.dt), gxT = T(A.ph.gx), gyT = T(A.ph.gy);
 
+    // LDS: partial moments (double-buffered by row) and wall fluxes; one
+    // allocation per kernel, shared by the wave variants
+    T (*sm)[3][SPLIT][64] = lds_moments<T, SPLIT>();
+    T (*sn)[SPLIT][64] = lds_wall<T, SPLIT>();
+
     for (int j = j0; j < j1; ++j) {
-        // new rows of the y window and this row's x halo
-        T nw[Q], hr[Q];
-#pragma unroll
-        for (int a = 0; a < Q; ++a) {
-            const double xq = TB::rule.x[a / N];
-            const int jn = xq < 0.0 ? j + 2 : j + 1;
-            nw[a] = ST::bld(rs, vl, LB_SOFF(a, jn));
-            hr[a] = ST::bld(rs, vh, LB_SOFF(a, j));
-        }
+        const bool more = j + 1 < j1;
+        const unsigned vln = more ? vl : OOB;
+        const bool own = valid && reg_of(lo_l, hi_l, j, g) == want;
+        const unsigned vs = own ? unsigned(col + 2) * EB : OOB;
+        const unsigned vimg_lo = (per_x && own && col < 2) ? unsigned(col + nx + 2) * EB : OOB;
+        const unsigned vimg_hi = (per_x && own && col >= nx - 2) ? unsigned(col - nx + 2) * EB : OOB;
+        const bool wall = g.ybc == YBC_WALLS && (j == 0 || j == g.ny);
+        const bool bottom = j == 0;
+        const int gj1 = bottom ? -1 : g.ny + 1, gj2 = bottom ? -2 : g.ny + 2;
+        T nacc = T(0);
 
         // moments of the centre values: rho' = sum f (shifted), j = sum xi f
         T rp = T(0), jx = T(0), jy = T(0);
 #pragma unroll
-        for (int q = 0; q < N; ++q) {
+        for (int qq = 0; qq < NQ; ++qq) {
             T sq = T(0), sxq = T(0);
 #pragma unroll
             for (int p = 0; p < N; ++p) {
-                sq += c[p + N * q];
-                sxq += T(TB::rule.x[p]) * c[p + N * q];
+                sq += c[p + N * qq];
+                sxq += T(TB::rule.x[p]) * c[p + N * qq];
             }
             rp += sq;
             jx += sxq;
-            jy += T(TB::rule.x[q]) * sq;
+            jy += T(TB::rule.x[q0 + qq]) * sq;
+        }
+        if constexpr (SPLIT > 1) {
+            const int buf = (j - j0) & 1;
+            sm[buf][0][wv][lane] = rp;
+            sm[buf][1][wv][lane] = jx;
+            sm[buf][2][wv][lane] = jy;
+            __syncthreads();
+            rp = sm[buf][0][0][lane];
+            jx = sm[buf][1][0][lane];
+            jy = sm[buf][2][0][lane];
+#pragma unroll
+            for (int w = 1; w < SPLIT; ++w) {
+                rp += sm[buf][0][w][lane];
+                jx += sm[buf][1][w][lane];
+                jy += sm[buf][2][w][lane];
+            }
         }
         const T rho = rho_shift + rp;
         const T inv = T(1) / rho;
@@ -550,7 +650,8 @@ __global__ __launch_bounds__(64) void k_update(const StepArgs A) {
             }
 
 #pragma unroll
-        for (int q = 0; q < N; ++q) {
+        for (int qq = 0; qq < NQ; ++qq) {
+            const int q = q0 + qq;
             // B_k(q) = w_q sum_m C_km He_m(x_q)/m!
             T B[EQ + 1];
 #pragma unroll
@@ -563,84 +664,266 @@ __global__ __launch_bounds__(64) void k_update(const StepArgs A) {
             const double xq = TB::rule.x[q];
 #pragma unroll
             for (int p = 0; p < N; ++p) {
+                const int k = p + N * qq;
                 const int a = p + N * q;
                 const double xp = TB::rule.x[p];
                 // source: (dt/tau) f_eq + dt g (shifted), separable in p and q
                 T Sa = T(0);
 #pragma unroll
-                for (int k = 0; k <= EQ; ++k) Sa += T(TB::rule.w[p] * TB::hk.v[k][p]) * B[k];
-                const T f = c[a];
+                for (int kx = 0; kx <= EQ; ++kx) Sa += T(TB::rule.w[p] * TB::hk.v[kx][p]) * B[kx];
+                const T f = c[k];
+                // f - om f keeps the relaxation rate exact to FP32 rounding of om
+                // ((1 - om) f would move it by eps/om relative)
                 T acc = f - om * f + Sa;
 
-                // x fluxes (DPP neighbours, halo at lanes 0 / 63)
+                // x fluxes: neighbours from the adjacent lanes
                 if (xp != 0.0) {
-                    const T fm1 = dpp<DPP_WAVE_SHR1>(f, hr[a]);
-                    const T fp1 = dpp<DPP_WAVE_SHL1>(f, hr[a]);
+                    const T fm1 = dpp<DPP_WAVE_SHR1>(f, f);
+                    const T fp1 = dpp<DPP_WAVE_SHL1>(f, f);
                     const T dm = f - fm1, dp = fp1 - f;
                     if (xp > 0.0) {
-                        const T h2 = dpp<DPP_WAVE_SHL1>(hr[a], hr[a]);   // lane 0 <- f(i0-2)
-                        const T dmm = dpp<DPP_WAVE_SHR1>(dm, fm1 - h2);
+                        const T dmm = dpp<DPP_WAVE_SHR1>(dm, dm);
                         const T Lp = minmod(dm, dp), Lm = minmod(dmm, dm);
                         acc = acc - nu[p] * dm - kk[p] * (Lp - Lm);
                     } else {
-                        const T h2 = dpp<DPP_WAVE_SHR1>(hr[a], hr[a]);   // lane 63 <- f(i0+65)
-                        const T dpp_ = dpp<DPP_WAVE_SHL1>(dp, h2 - fp1);
+                        const T dpp_ = dpp<DPP_WAVE_SHL1>(dp, dp);
                         const T Lp = minmod(dpp_, dp), Lm = minmod(dp, dm);
                         acc = acc - nu[p] * dp - kk[p] * (Lp - Lm);
                     }
                 }
                 // y fluxes (register window)
                 if (xq > 0.0) {
-                    const T dp = nw[a] - f;
-                    const T Lp = minmod(s1[a], dp);
-                    acc = acc - nu[q] * s1[a] - kk[q] * (Lp - s2[a]);
-                    c[a] = nw[a];
-                    s1[a] = dp;
-                    s2[a] = Lp;
+                    const T dp = nw[k] - f;
+                    const T Lp = minmod(s1[k], dp);
+                    acc = acc - nu[q] * s1[k] - kk[q] * (Lp - s2[k]);
+                    c[k] = nw[k];
+                    s1[k] = dp;
+                    s2[k] = Lp;
                 } else if (xq < 0.0) {
-                    const T d = s1[a] - f, dn = nw[a] - s1[a];
+                    const T d = s1[k] - f, dn = nw[k] - s1[k];
                     const T Lp = minmod(dn, d);
-                    acc = acc - nu[q] * d - kk[q] * (Lp - s2[a]);
-                    c[a] = s1[a];
-                    s1[a] = nw[a];
-                    s2[a] = Lp;
+                    acc = acc - nu[q] * d - kk[q] * (Lp - s2[k]);
+                    c[k] = s1[k];
+                    s1[k] = nw[k];
+                    s2[k] = Lp;
                 } else {
-                    c[a] = nw[a];
+                    c[k] = nw[k];
                 }
+                // next row of this population (zero-cost past the strip end)
+                nw[k] = ST::bld(rs, vln, LB_SOFF(a, xq < 0.0 ? j + 3 : j + 2));
+
                 ST::bst(rd, vs, LB_SOFF(a, j), acc);
                 if (wave_img) {
                     ST::bst(rd, vimg_lo, LB_SOFF(a, j), acc);
                     ST::bst(rd, vimg_hi, LB_SOFF(a, j), acc);
                 }
+                if (wall) {
+                    // into the wall: bottom xi_y < 0, top xi_y > 0; those and
+                    // xi_y = 0 are final: copy them to the ghost rows
+                    const bool leaving = bottom ? (xq > 0.0) : (xq < 0.0);
+                    if (!leaving) {
+                        if (xq != 0.0) nacc += T(lbt::cabs(xq)) * acc;
+                        ST::bst(rd, vs, LB_SOFF(a, gj1), acc);
+                        ST::bst(rd, vs, LB_SOFF(a, gj2), acc);
+                    }
+                }
+                // keep the scheduler from hoisting every population's
+                // neighbour arithmetic to the top of the row (register blow-up)
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
-
+        if (wall) {
+            const int ws = bottom ? 0 : 1;
+            if constexpr (SPLIT > 1) {
+                sn[ws][wv][lane] = nacc;
+                __syncthreads();
+                nacc = sn[ws][0][lane];
+#pragma unroll
+                for (int w = 1; w < SPLIT; ++w) nacc += sn[ws][w][lane];
+            }
+            T Kw, Dw;
+            if constexpr (sizeof(T) == 8) {
+                Kw = A.ks.wK[ws];
+                Dw = A.ks.wD[ws];
+            } else {
+                Kw = A.ks.wKf[ws];
+                Dw = A.ks.wDf[ws];
+            }
+            const T d = (nacc - rho_shift * Dw) / (Kw + Dw);
+#pragma unroll
+            for (int k = 0; k < QW; ++k) {
+                const int a = LB_POP(k);
+                const double xq = TB::rule.x[q0 + k / N];
+                if (xq == 0.0) continue;
+                if (bottom != (xq > 0.0)) continue;   // leaving the wall only
+                T sp;
+                if constexpr (sizeof(T) == 8) sp = A.ks.sp[ws][a];
+                else sp = A.ks.spf[ws][a];
+                const T fl = d * T(TB::rule.w[a % N] * TB::rule.w[a / N]) + (d + rho_shift) * sp;
+                ST::bst(rd, vs, LB_SOFF(a, j), fl);
+                ST::bst(rd, vs, LB_SOFF(a, gj1), fl);
+                ST::bst(rd, vs, LB_SOFF(a, gj2), fl);
+                if (wave_img) {
+                    ST::bst(rd, vimg_lo, LB_SOFF(a, j), fl);
+                    ST::bst(rd, vimg_hi, LB_SOFF(a, j), fl);
+                }
+            }
+        }
     }
 #undef LB_SOFF
+#undef LB_POP
 }
 
-// Second pass of a step over the special nodes of both sets (list built on
-// the host when the regions change): entry = (i, j, set, flags) with flags
-// 1 = wall row, 2 = row image, 4 = pressure column, 8 = read by the partner
-// set.  A.self is the low set's buffer, A.other the high set's.
-template <class ST, class SS, class OO>
-__device__ void finish_entry(const Buf &self, const Buf &other, int copy, int i, int j, int flags,
-                             const StepArgs &A) {
-    double f[SS::Q];
-    load_node_d<ST, SS>(self, copy, i, j, A.rho_shift, f);
-    const bool wall = flags & 1;
-    if (wall) diffuse_wall_d<SS>(f, j == A.g.ny, A.ph);
-    finish_node<ST, SS, OO>(self, other, copy, i, j, A.rho_shift, f, wall, (flags & 8) != 0, A.g, A.ph);
-}
-
+// Row images (periodic y) and pressure columns of the nodes listed in
+// A.items (i, j, set, 0): node-local, from the freshly written copy.
 template <class ST, class LS, class HS>
 __global__ __launch_bounds__(128) void k_finish(const StepArgs A) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= A.nitems) return;
-    const int i = A.items[4 * k], j = A.items[4 * k + 1], set = A.items[4 * k + 2], flags = A.items[4 * k + 3];
+    const int i = A.items[4 * k], j = A.items[4 * k + 1], set = A.items[4 * k + 2];
     const int copy = A.cur ^ 1;
-    if (set == 0) finish_entry<ST, LS, HS>(A.self, A.other, copy, i, j, flags, A);
-    else finish_entry<ST, HS, LS>(A.other, A.self, copy, i, j, flags, A);
+    if (set == 0) {
+        double f[LS::Q];
+        load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, f);
+        emit_node<ST, LS>(A.self, copy, i, j, A.rho_shift, f, false, A.g, A.ph);
+    } else {
+        double f[HS::Q];
+        load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, f);
+        emit_node<ST, HS>(A.other, copy, i, j, A.rho_shift, f, false, A.g, A.ph);
+    }
+}
+
+// One population t of the projection of a source node (set SS, absolute
+// values fs) onto set DD; also returns rho, u of the node.
+template <class SS, class DD>
+__device__ double project_one(const double *fs, int t, double &rho, double &ux, double &uy) {
+    using TS = typename SS::T;
+    using TD = typename DD::T;
+    constexpr int NS = SS::N, ND = DD::N;
+    constexpr int NM = NS < ND ? NS : ND;
+    double tt[NS][NM];
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) s += fs[p + NS * q] * TS::he.v[m][q];
+            tt[p][m] = s;
+        }
+    double a[NM][NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < NS; ++p) s += TS::he.v[k][p] * tt[p][m];
+            a[k][m] = s;
+        }
+    rho = a[0][0];
+    ux = a[1][0] / rho;
+    uy = a[0][1] / rho;
+    if constexpr (SS::N == DD::N && SS::EQ == DD::EQ) {
+        return fs[t];
+    } else {
+        double px[ND + 1], py[ND + 1];
+        px[0] = py[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k <= ND; ++k) {
+            px[k] = px[k - 1] * ux;
+            py[k] = py[k - 1] * uy;
+        }
+        const int tp = t % ND, tq = t / ND;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            double b = 0.0;
+#pragma unroll
+            for (int m = 0; m < ND; ++m) {
+                double eqd = (k + m <= DD::EQ) ? rho * px[k] * py[m] : 0.0;
+                double neq = 0.0;
+                if (k < NM && m < NM) neq = a[k][m] - ((k + m <= SS::EQ) ? rho * px[k] * py[m] : 0.0);
+                b += (eqd + neq) * TD::hk.v[m][tq];
+            }
+            s += TD::hk.v[k][tp] * b;
+        }
+        return TD::rule.w[tp] * TD::rule.w[tq] * s;
+    }
+}
+
+// one population of the order-EQ equilibrium (absolute)
+template <class SS>
+__device__ double feq_one(double rho, double ux, double uy, int t) {
+    using TB = typename SS::T;
+    const int tp = t % SS::N, tq = t / SS::N;
+    double s = 0.0, pk = 1.0;
+#pragma unroll
+    for (int k = 0; k <= SS::EQ; ++k) {
+        double b = 0.0, pm = 1.0;
+#pragma unroll
+        for (int m = 0; m + k <= SS::EQ; ++m) {
+            b += pm * TB::hk.v[m][tq];
+            pm *= uy;
+        }
+        s += pk * TB::hk.v[k][tp] * b;
+        pk *= ux;
+    }
+    return TB::rule.w[tp] * TB::rule.w[tq] * rho * s;
+}
+
+// store one population t of set SS at node (i, j) and at every ghost entry
+// standing for it (the per-population form of emit_node)
+template <class ST, class SS>
+__device__ void emit_pop(const Buf &b, int copy, int i, int j, double shift, int t, double v, double rho,
+                         double ux, double uy, const Geo &g, const Phys &ph) {
+    typename ST::S *p0 = plane0<ST, SS>(b, copy) + (int64_t)t * b.plane;
+    const double sv = v - w_of<SS>(t) * shift;
+    auto put = [&](int ii, int jj, double x) { ST::std_(p0 + (int64_t)(jj + 2) * b.pitch + ii, x); };
+    put(i, j, sv);
+    if (g.ybc == YBC_WALLS) {
+        if (j == 0) { put(i, -1, sv); put(i, -2, sv); }
+        if (j == g.ny) { put(i, g.ny + 1, sv); put(i, g.ny + 2, sv); }
+    } else {
+        if (j < 2) put(i, j + g.nrow, sv);
+        if (j >= g.nrow - 2) put(i, j - g.nrow, sv);
+    }
+    if (g.xbc == XBC_PERIODIC) {
+        if (i < 2) put(i + g.nx, j, sv);
+        if (i >= g.nx - 2) put(i - g.nx, j, sv);
+    } else if (i == 0 || i == g.nx - 1) {
+        const double gv = feq_one<SS>(i == 0 ? ph.rho_in : ph.rho_out, ux, uy, t) + (v - feq_one<SS>(rho, ux, uy, t)) -
+                          w_of<SS>(t) * shift;
+        if (i == 0) { put(-1, j, gv); put(-2, j, gv); }
+        else { put(g.nx, j, gv); put(g.nx + 1, j, gv); }
+    }
+}
+
+// Hermite-moment projection of the halo-source nodes into the partner set,
+// one thread per (node, target population).  A.items lists (i, j) pairs:
+// the first A.nitems nodes of the low set project into the high set, the
+// next A.chunk nodes of the high set into the low set.
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n0 = (int64_t)A.nitems * HS::Q, n1 = (int64_t)A.chunk * LS::Q;
+    const int copy = A.cur ^ 1;
+    double rho, ux, uy;
+    if (k < n0) {
+        const int e = int(k / HS::Q), t = int(k % HS::Q);
+        const int i = A.items[2 * e], j = A.items[2 * e + 1];
+        double fs[LS::Q];
+        load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, fs);
+        const double v = project_one<LS, HS>(fs, t, rho, ux, uy);
+        emit_pop<ST, HS>(A.other, copy, i, j, A.rho_shift, t, v, rho, ux, uy, A.g, A.ph);
+    } else if (k < n0 + n1) {
+        const int e = int((k - n0) / LS::Q) + A.nitems, t = int((k - n0) % LS::Q);
+        const int i = A.items[2 * e], j = A.items[2 * e + 1];
+        double fs[HS::Q];
+        load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, fs);
+        const double v = project_one<HS, LS>(fs, t, rho, ux, uy);
+        emit_pop<ST, LS>(A.self, copy, i, j, A.rho_shift, t, v, rho, ux, uy, A.g, A.ph);
+    }
 }
 
 // ------------------------------------------------------ per-node kernels

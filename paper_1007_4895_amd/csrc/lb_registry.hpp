@@ -11,6 +11,7 @@
 namespace lbk {
 
 using StepFn = void (*)(const lbi::StepArgs &, int grid, hipStream_t);
+using TimedFn = void (*)(const lbi::StepArgs &, int grid, hipStream_t, hipEvent_t start, hipEvent_t stop);
 using NodeFn = void (*)(const lbi::NodeArgs &, int grid, hipStream_t);
 using IfaceFn = void (*)(const lbi::NodeArgs &, int copy, int recompute, int grid, hipStream_t);
 using ProjFn = void (*)(const double *, const double *, double *, int64_t, hipStream_t);
@@ -18,7 +19,9 @@ using ProjFn = void (*)(const double *, const double *, double *, int64_t, hipSt
 struct KernelSet {
     int storage, nS, eqS, nO, eqO;
     StepFn update;
-    StepFn finish;   // valid when `self` is the low set of the pair
+    TimedFn update_timed;   // the same launch bracketed by kernel start/stop events
+    StepFn finish;        // valid when `self` is the low set of the pair
+    StepFn project_halo;  // likewise
     NodeFn refresh, init_eq, set_pop, get_pop, moments, indicator, convert;
     IfaceFn paper_iface;   // valid when `self` is the low set of the pair
     ProjFn project;        // FP64 projection self -> partner

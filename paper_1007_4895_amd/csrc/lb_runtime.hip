@@ -3,9 +3,10 @@
 // Owns no device memory: everything lives in the caller's workspace, carved
 // up by ws_layout().  All work is enqueued on the caller's stream.  A time
 // step is: one k_update launch per velocity set (work items = 64 columns x a
-// strip of rows of that set), then one k_finish launch over the list of
-// special nodes (walls, images, pressure columns, nodes the partner set
-// reads), then, in the interpolation/extrapolation interface mode, the
+// strip of rows of that set; walls are handled there), then the projection
+// of the halo-source nodes into the partner set (one thread per node and
+// target population), then -- only where present -- row images and pressure
+// columns, and in the interpolation/extrapolation interface mode the
 // interface-row kernel.
 #include <hip/hip_runtime.h>
 
@@ -74,7 +75,7 @@ struct Layout {
     int64_t plane[2];
     size_t off_pop[2][2];   // [set][copy]
     size_t off_blo, off_bhi, off_oblo, off_obhi;
-    size_t off_items[2], off_fin, off_stage, off_mom, off_part;
+    size_t off_items[2], off_fin, off_proj, off_stage, off_mom, off_part;
     int maxitems, maxfin;
     size_t stage_elems;
     size_t total;
@@ -108,14 +109,15 @@ Layout ws_layout(const lb_params &p) {
     L.off_bhi = off; off = align_up(off + 4 * nt, 256);
     L.off_oblo = off; off = align_up(off + 4 * nt, 256);
     L.off_obhi = off; off = align_up(off + 4 * nt, 256);
-    const int ncolw = (p.nx + 63) / 64;
-    L.maxitems = ncolw * (nrow + 4);
+    const int ngrp = (p.nx + 59) / 60;
+    L.maxitems = 8 * (ngrp / 8 + 1) * (nrow + 4);
     for (int s = 0; s < 2; ++s) {
         L.off_items[s] = off;
         off = align_up(off + 16 * size_t(L.maxitems), 256);
     }
     L.maxfin = int(nodes);
     L.off_fin = off; off = align_up(off + 16 * nodes, 256);
+    L.off_proj = off; off = align_up(off + 8 * nodes, 256);
     int qmax = std::max(std::max(n[0] * n[0], n[1] * n[1]), 3);
     L.stage_elems = size_t(qmax) * nodes;
     L.off_stage = off; off = align_up(off + 8 * L.stage_elems, 256);
@@ -147,6 +149,45 @@ int host_reg(int lo, int hi, int j, int ny, int iface) {
     if (j < lo || j > ny - hi) return REG_HIGH;
     if (iface == IF_PAPER && ((lo > 0 && j == lo) || (hi > 0 && j == ny - hi))) return REG_IFACE;
     return REG_LOW;
+}
+
+// Diffuse-wall constants of a set (Sec. 3.2): S = f_eq(rho = 1, u_wall) of
+// the set's order, stored as S' = S - w (computed without cancellation),
+// K = sum_leaving |xi_y| w and D' = sum_leaving |xi_y| S', where the
+// populations leaving the bottom wall have xi_y > 0 and those leaving the
+// top wall xi_y < 0.
+void wall_constants(int n, int eq, const double *x, const double *w, const double *uw, SetK &k) {
+    for (int ws = 0; ws < 2; ++ws) {
+        const double u = uw[2 * ws], v = uw[2 * ws + 1];
+        double K = 0.0, D = 0.0;
+        for (int q = 0; q < n; ++q)
+            for (int p = 0; p < n; ++p) {
+                const int a = p + n * q;
+                double s = 0.0, pk = 1.0;
+                for (int kx = 0; kx <= eq; ++kx) {
+                    double pm = 1.0;
+                    for (int m = 0; m + kx <= eq; ++m) {
+                        if (kx + m > 0)
+                            s += pk * pm * lbt::hermite(kx, x[p]) * lbt::hermite(m, x[q]) /
+                                 (lbt::factorial(kx) * lbt::factorial(m));
+                        pm *= v;
+                    }
+                    pk *= u;
+                }
+                const double sp = w[p] * w[q] * s;
+                k.sp[ws][a] = sp;
+                k.spf[ws][a] = float(sp);
+                const bool leaving = ws == 0 ? x[q] > 0.0 : x[q] < 0.0;
+                if (leaving) {
+                    K += std::fabs(x[q]) * w[p] * w[q];
+                    D += std::fabs(x[q]) * sp;
+                }
+            }
+        k.wK[ws] = K;
+        k.wD[ws] = D;
+        k.wKf[ws] = float(K);
+        k.wDf[ws] = float(D);
+    }
 }
 
 // ------------------------------------------------ generic (untemplated) kernels
@@ -231,9 +272,12 @@ struct lb_lattice {
     int32_t *d_blo, *d_bhi, *d_oblo, *d_obhi;
     int32_t *d_items[2];
     int nitems[2];
-    int32_t *d_fin;
+    int32_t *d_fin;      // row images / pressure columns: (i, j, set, 0)
     int nfin;
-    int strip;
+    int32_t *d_proj;     // halo sources: (i, j), low-set nodes first
+    int nproj[2];
+    int strip[2];        // rows per work item per set (0 = automatic)
+    int order[2];        // item order per set: 0 = XCD slabs row-major, 1 = column-major
     double *d_stage, *d_mom, *d_part;
     bool timing;
     std::vector<hipEvent_t> ev_pool;
@@ -260,43 +304,93 @@ NodeArgs node_args(const lb_lattice *L, int s, int copy) {
 
 int node_grid(const lb_lattice *L) { return (L->geo.nrow * L->geo.nx + 255) / 256; }
 
-// work items of set s: maximal runs of rows of that set per 64-column wave,
-// cut into strips; the list is ordered column-major so neighbouring strips
-// are consecutive (and land on the same XCD through the kernel's mapping)
+// work items of set s: per 60-column group (the columns a block of the
+// update kernel writes), the maximal runs of rows in which any column of
+// the group belongs to the set, cut into strips; the list is ordered
+// column-major so neighbouring strips are consecutive (and land on the same
+// XCD through the kernel's mapping)
 int build_items(const lb_lattice *L, int s, std::vector<int32_t> &out) {
     out.clear();
     const int nx = L->p.nx, ny = L->p.ny, nrow = ny + 1;
     const int want = s ? REG_HIGH : REG_LOW;
-    const int ncolw = (nx + 63) / 64;
+    const int ngrp = (nx + 59) / 60;
     int rows = 0;
     std::vector<std::pair<int, int>> runs;
     std::vector<int> runcol;
-    for (int w = 0; w < ncolw; ++w) {
-        const int i0 = 64 * w;
-        const int t = L->ntiles == 1 ? 0 : i0 / L->tile_w;
+    std::vector<char> inset(nrow);
+    for (int w = 0; w < ngrp; ++w) {
+        const int i0 = 60 * w, i1 = std::min(i0 + 60, nx);
+        const int t0 = L->ntiles == 1 ? 0 : i0 / L->tile_w, t1 = L->ntiles == 1 ? 0 : (i1 - 1) / L->tile_w;
+        for (int j = 0; j < nrow; ++j) {
+            inset[j] = 0;
+            for (int t = t0; t <= t1; ++t)
+                if (host_reg(L->blo[t], L->bhi[t], j, ny, L->p.iface) == want) inset[j] = 1;
+        }
         int j = 0;
         while (j < nrow) {
-            if (host_reg(L->blo[t], L->bhi[t], j, ny, L->p.iface) != want) {
+            if (!inset[j]) {
                 ++j;
                 continue;
             }
             int j1 = j;
-            while (j1 < nrow && host_reg(L->blo[t], L->bhi[t], j1, ny, L->p.iface) == want) ++j1;
+            while (j1 < nrow && inset[j1]) ++j1;
             runs.push_back({j, j1});
             runcol.push_back(i0);
             rows += j1 - j;
             j = j1;
         }
     }
-    int strip = L->strip;
-    if (strip <= 0) strip = std::max(1, std::min(16, rows / 2048));
+    int strip = L->strip[s];
+    if (strip <= 0) {
+        // enough blocks to give every CU a few resident ones
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        strip = std::max(1, std::min(16, rows / (8 * cus)));
+    }
+    // Item order: the kernel gives XCD x the items [x * chunk, (x + 1) * chunk).
+    // Each XCD gets a contiguous slab of column groups, and inside the slab
+    // the strips are ordered row-major: blocks running together touch
+    // neighbouring groups of the same rows (they share the edge cache lines
+    // of their overlapping loads in that XCD's L2, and HBM sees long runs),
+    // and the next strip up finds its two halo rows still in the same L2.
+    // Slabs are padded with empty items to a common length.
+    struct It { int slab, j0, i0, j1; };
+    std::vector<It> v;
     for (size_t r = 0; r < runs.size(); ++r)
         for (int j = runs[r].first; j < runs[r].second; j += strip) {
-            out.push_back(runcol[r]);
-            out.push_back(j);
-            out.push_back(std::min(j + strip, runs[r].second));
-            out.push_back(0);
+            const int g = runcol[r] / 60;
+            v.push_back({int(int64_t(g) * 8 / ngrp), j, runcol[r], std::min(j + strip, runs[r].second)});
         }
+    if (ngrp < 8 || L->order[s] == 1) {
+        // too few column groups for one per XCD (or column-major order
+        // requested): cut the ordered list into 8 contiguous pieces instead
+        const bool cm = L->order[s] == 1;
+        std::sort(v.begin(), v.end(), [cm](const It &a, const It &b) {
+            if (cm) return a.i0 != b.i0 ? a.i0 < b.i0 : a.j0 < b.j0;
+            return a.j0 != b.j0 ? a.j0 < b.j0 : a.i0 < b.i0;
+        });
+        for (size_t k = 0; k < v.size(); ++k) v[k].slab = int(k * 8 / v.size());
+    }
+    const bool colmajor = L->order[s] == 1;
+    std::sort(v.begin(), v.end(), [colmajor](const It &a, const It &b) {
+        if (a.slab != b.slab) return a.slab < b.slab;
+        if (colmajor) return a.i0 != b.i0 ? a.i0 < b.i0 : a.j0 < b.j0;
+        if (a.j0 != b.j0) return a.j0 < b.j0;
+        return a.i0 < b.i0;
+    });
+    int per[8] = {0};
+    for (auto &e : v) per[e.slab]++;
+    int chunk = 0;
+    for (int x = 0; x < 8; ++x) chunk = std::max(chunk, per[x]);
+    out.assign(size_t(8) * chunk * 4, 0);
+    int fill[8] = {0};
+    for (auto &e : v) {
+        int k = e.slab * chunk + fill[e.slab]++;
+        out[4 * k] = e.i0;
+        out[4 * k + 1] = e.j0;
+        out[4 * k + 2] = e.j1;
+        out[4 * k + 3] = 0;
+    }
     return int(out.size() / 4);
 }
 
@@ -324,31 +418,38 @@ bool host_neighbour_in(const lb_lattice *L, int i, int j, int want) {
     return false;
 }
 
-// special nodes of both sets: (i, j, set, flags) with flags 1 = wall,
-// 2 = row image, 4 = pressure column, 8 = read by the partner set
-int build_finish(const lb_lattice *L, std::vector<int32_t> &out) {
-    out.clear();
+// Per-step lists: `fin` = nodes needing row images (periodic y) or pressure
+// columns, as (i, j, set, 0); `proj` = nodes a stencil of the partner set
+// reads (Hermite interface), as (i, j), low-set nodes first.
+int build_lists(const lb_lattice *L, std::vector<int32_t> &fin, std::vector<int32_t> &proj, int nproj[2]) {
+    fin.clear();
+    proj.clear();
+    std::vector<int32_t> ph;
     const int nx = L->p.nx, ny = L->p.ny, nrow = ny + 1;
     for (int j = 0; j < nrow; ++j)
         for (int i = 0; i < nx; ++i) {
             int t = L->ntiles == 1 ? 0 : i / L->tile_w;
             int r = host_reg(L->blo[t], L->bhi[t], j, ny, L->p.iface);
             if (r == REG_IFACE) continue;
-            int flags = 0;
-            if (L->p.ybc == LB_YBC_WALLS && (j == 0 || j == ny)) flags |= 1;
-            if (L->p.ybc == LB_YBC_PERIODIC && (j < 2 || j >= nrow - 2)) flags |= 2;
-            if (L->p.xbc == LB_XBC_PRESSURE && (i == 0 || i == nx - 1)) flags |= 4;
-            if (L->p.iface == LB_IFACE_HERMITE &&
-                host_neighbour_in(L, i, j, r == REG_HIGH ? REG_LOW : REG_HIGH))
-                flags |= 8;
-            if (flags) {
-                out.push_back(i);
-                out.push_back(j);
-                out.push_back(r == REG_HIGH ? 1 : 0);
-                out.push_back(flags);
+            const int set = r == REG_HIGH ? 1 : 0;
+            bool misc = (L->p.ybc == LB_YBC_PERIODIC && (j < 2 || j >= nrow - 2)) ||
+                        (L->p.xbc == LB_XBC_PRESSURE && (i == 0 || i == nx - 1));
+            if (misc) {
+                fin.push_back(i);
+                fin.push_back(j);
+                fin.push_back(set);
+                fin.push_back(0);
+            }
+            if (L->p.iface == LB_IFACE_HERMITE && host_neighbour_in(L, i, j, set ? REG_LOW : REG_HIGH)) {
+                std::vector<int32_t> &dst = set ? ph : proj;
+                dst.push_back(i);
+                dst.push_back(j);
             }
         }
-    return int(out.size() / 4);
+    nproj[0] = int(proj.size() / 2);
+    nproj[1] = int(ph.size() / 2);
+    proj.insert(proj.end(), ph.begin(), ph.end());
+    return int(fin.size() / 4);
 }
 
 lb_status upload_regions(lb_lattice *L) {
@@ -369,8 +470,10 @@ lb_status upload_regions(lb_lattice *L) {
             L->count[host_reg(L->blo[t], L->bhi[t], j, L->p.ny, L->p.iface)] += w;
         }
     L->dom = double(L->Q[1]) * L->count[1] > double(L->Q[0]) * L->count[0] ? 1 : 0;
-    L->nfin = build_finish(L, v);
+    std::vector<int32_t> pv;
+    L->nfin = build_lists(L, v, pv, L->nproj);
     if (L->nfin) HIPCHK(hipMemcpyAsync(L->d_fin, v.data(), v.size() * 4, hipMemcpyHostToDevice, L->stream));
+    if (!pv.empty()) HIPCHK(hipMemcpyAsync(L->d_proj, pv.data(), pv.size() * 4, hipMemcpyHostToDevice, L->stream));
     HIPCHK(hipStreamSynchronize(L->stream));
     return LB_OK;
 }
@@ -436,20 +539,25 @@ lb_status one_step(lb_lattice *L) {
         a.items = L->d_items[s];
         a.nitems = L->nitems[s];
         a.chunk = (a.nitems + 7) / 8;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
         if (L->timing) {
-            e0 = next_event(L);
-            e1 = next_event(L);
+            hipEvent_t e0 = next_event(L), e1 = next_event(L);
             if (!e0 || !e1) return fail(LB_EDEVICE, "event creation failed");
-            L->ev_kind.push_back(s == L->dom ? 1 : 0);
-            HIPCHK(hipEventRecord(e0, L->stream));
+            L->ev_kind.push_back(s);
+            L->ks[s]->update_timed(a, 8 * a.chunk, L->stream, e0, e1);
+        } else {
+            L->ks[s]->update(a, 8 * a.chunk, L->stream);
         }
-        L->ks[s]->update(a, 8 * a.chunk, L->stream);
-        if (L->timing) HIPCHK(hipEventRecord(e1, L->stream));
+    }
+    a.self = L->buf[0];
+    a.other = L->buf[1];
+    if (L->nproj[0] + L->nproj[1]) {
+        a.items = L->d_proj;
+        a.nitems = L->nproj[0];
+        a.chunk = L->nproj[1];
+        const int64_t nt = int64_t(L->nproj[0]) * L->Q[1] + int64_t(L->nproj[1]) * L->Q[0];
+        L->ks[0]->project_halo(a, int((nt + 127) / 128), L->stream);
     }
     if (L->nfin) {
-        a.self = L->buf[0];
-        a.other = L->buf[1];
         a.items = L->d_fin;
         a.nitems = L->nfin;
         L->ks[0]->finish(a, (L->nfin + 127) / 128, L->stream);
@@ -569,6 +677,7 @@ lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t byte
     for (int s = 0; s < 2; ++s) {
         double x[8] = {0}, w[8] = {0};
         abscissae(L->n[s], x, w);
+        wall_constants(L->n[s], L->eq[s], x, w, p->u_wall, L->kconst[s]);
         for (int q = 0; q < 8; ++q) {
             double nu = x[q] * L->dt, an = std::fabs(nu);
             L->kconst[s].nu[q] = nu;
@@ -593,10 +702,12 @@ lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t byte
     L->d_obhi = reinterpret_cast<int32_t *>(L->ws + lay.off_obhi);
     for (int s = 0; s < 2; ++s) L->d_items[s] = reinterpret_cast<int32_t *>(L->ws + lay.off_items[s]);
     L->d_fin = reinterpret_cast<int32_t *>(L->ws + lay.off_fin);
+    L->d_proj = reinterpret_cast<int32_t *>(L->ws + lay.off_proj);
     L->d_stage = reinterpret_cast<double *>(L->ws + lay.off_stage);
     L->d_mom = reinterpret_cast<double *>(L->ws + lay.off_mom);
     L->d_part = reinterpret_cast<double *>(L->ws + lay.off_part);
-    L->strip = 0;
+    L->strip[0] = L->strip[1] = 0;
+    L->order[0] = L->order[1] = 0;
     L->cur = 0;
     L->step = 0;
     L->blo.assign(L->ntiles, 0);
@@ -652,8 +763,68 @@ lb_status lb_region_counts(const lb_lattice *L, int64_t counts[3]) {
 
 lb_status lb_set_strip_rows(lb_lattice *L, int32_t rows) {
     if (!L || rows < 0 || rows > 1024) return fail(LB_EINVAL, "strip rows in [0, 1024] (0 = automatic)");
-    L->strip = rows;
+    L->strip[0] = L->strip[1] = rows;
     return upload_regions(L);
+}
+
+lb_status lb_get_strip_rows(const lb_lattice *L, int32_t rows[2]) {
+    if (!L || !rows) return fail(LB_EINVAL, "null argument");
+    rows[0] = L->strip[0];
+    rows[1] = L->strip[1];
+    return LB_OK;
+}
+
+lb_status lb_autotune(lb_lattice *L, int32_t steps, int32_t rows_out[2]) {
+    if (!L || steps < 1) return fail(LB_EINVAL, "bad argument");
+    if (!L->initialized) return fail(LB_ESTATE, "lattice not initialised");
+    // the trials advance the lattice: keep the state and restore it after
+    std::vector<char> saved(lb_state_bytes(L));
+    lb_status st = lb_get_state(L, saved.data(), saved.size());
+    if (st != LB_OK) return st;
+    const int cur0 = L->cur;
+    static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
+    for (int s = 0; s < 2; ++s) {
+        if (!L->count[s]) continue;
+        double best = 1e300;
+        int best_rows = 1, best_order = 0;
+        for (int cc = 0; cc < 2 * int(sizeof(cand) / sizeof(cand[0])); ++cc) {
+            const int c = cand[cc >> 1], ord = cc & 1;
+            L->strip[s] = c;
+            L->order[s] = ord;
+            if ((st = upload_regions(L)) != LB_OK) return st;
+            L->timing = true;
+            L->ev_used = 0;
+            L->ev_kind.clear();
+            for (int k = 0; k < steps; ++k)
+                if ((st = one_step(L)) != LB_OK) return st;
+            HIPCHK(hipStreamSynchronize(L->stream));
+            double t = 0;
+            for (size_t k = 0; k < L->ev_kind.size(); ++k) {
+                if (L->ev_kind[k] != s) continue;
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, L->ev_pool[2 * k], L->ev_pool[2 * k + 1]));
+                t += ms;
+            }
+            if (t < best) {
+                best = t;
+                best_rows = c;
+                best_order = ord;
+            }
+        }
+        L->strip[s] = best_rows;
+        L->order[s] = best_order;
+    }
+    L->timing = false;
+    L->ev_used = 0;
+    L->ev_kind.clear();
+    if ((st = upload_regions(L)) != LB_OK) return st;
+    L->cur = cur0;
+    st = lb_set_state(L, saved.data(), saved.size());
+    if (rows_out) {
+        rows_out[0] = L->strip[0];
+        rows_out[1] = L->strip[1];
+    }
+    return st;
 }
 
 lb_status lb_init_equilibrium(lb_lattice *L, const double *rho, const double *ux, const double *uy) {
@@ -899,7 +1070,7 @@ lb_status lb_kernel_times(lb_lattice *L, double *ms_high, int64_t *n_high, doubl
         HIPCHK(hipEventElapsedTime(&ms, L->ev_pool[2 * k], L->ev_pool[2 * k + 1]));
         ma += ms;
         na++;
-        if (L->ev_kind[k]) {
+        if (L->ev_kind[k] == L->dom) {
             mh += ms;
             nh++;
         }

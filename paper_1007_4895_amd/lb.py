@@ -85,6 +85,8 @@ def lib():
             "lb_kernel_times": (C.c_int, [_vp, _dp, C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int64)]),
             "lb_set_strip_rows": (C.c_int, [_vp, C.c_int32]),
             "lb_region_counts": (C.c_int, [_vp, C.POINTER(C.c_int64)]),
+            "lb_get_strip_rows": (C.c_int, [_vp, _ip]),
+            "lb_autotune": (C.c_int, [_vp, C.c_int32, _ip]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -195,6 +197,18 @@ class Lattice:
 
     def set_strip_rows(self, rows):
         _check(lib().lb_set_strip_rows(self._h, rows))
+
+    def strip_rows(self):
+        r = (C.c_int32 * 2)()
+        _check(lib().lb_get_strip_rows(self._h, r))
+        return tuple(r)
+
+    def autotune(self, steps=50):
+        """Pick the strip height of each set's update kernel by timing
+        candidates; the lattice state is restored afterwards."""
+        r = (C.c_int32 * 2)()
+        _check(lib().lb_autotune(self._h, steps, r))
+        return tuple(r)
 
     # ----------------------------------------------------------------- state
     def init_equilibrium(self, rho=None, ux=None, uy=None):

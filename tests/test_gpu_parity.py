@@ -238,6 +238,20 @@ def test_strip_rows_invariance_and_determinism(lb):
             np.testing.assert_array_equal(x, y)
 
 
+def test_autotune_restores_state(lb):
+    G = lb.Lattice(lb.make_params(256, 60, kn=0.1, n_low=3, n_high=6, eq_low=2, eq_high=4, storage="f32",
+                                  gx=1e-5, u_wall=((0.01, 0.0), (-0.01, 0.0))))
+    G.set_regions(12, 12)
+    G.init_equilibrium()
+    G.step(20)
+    before = (G.get_populations(0), G.get_populations(1), G.steps)
+    rows = G.autotune(5)
+    assert all(r >= 1 for r in rows) and G.strip_rows() == rows
+    assert G.steps == before[2]
+    np.testing.assert_array_equal(G.get_populations(0), before[0])
+    np.testing.assert_array_equal(G.get_populations(1), before[1])
+
+
 def test_checkpoint_resume_bitwise(lb):
     def make():
         G = lb.Lattice(lb.make_params(96, 40, kn=0.1, n_low=3, n_high=4, eq_low=2, eq_high=3, storage="f32",
@@ -311,8 +325,10 @@ def test_region_change_and_indicator(oracle, lb):
     Bo, Bg = O.indicator(), G.indicator()
     assert np.max(np.abs(Bg - Bo)) < 1e-12 * max(1.0, np.max(Bo))
     # bands from the indicator: bit-exact away from the threshold
-    Bs = np.unique(Bo)
-    k = int(0.7 * len(Bs))
+    # threshold in the widest gap between indicator values in the upper half
+    Bs = np.sort(Bo.ravel())
+    lo_k = len(Bs) // 2
+    k = lo_k + int(np.argmax(np.diff(Bs[lo_k:])))
     theta = float(0.5 * (Bs[k] + Bs[k + 1]))
     bo = O.bands_from_indicator(Bo, theta, 2, 20)
     G.update_regions(theta, 2, 20)
