@@ -337,3 +337,56 @@ def test_region_change_and_indicator(oracle, lb):
     assert guard.sum() == 0
     np.testing.assert_array_equal(bg[0], bo[0])
     np.testing.assert_array_equal(bg[1], bo[1])
+
+
+# ----------------------------------------------- pressure channel with regrid
+def _c3_small(oracle, lb, storage, regrid):
+    nx, ny, tw = 256, 48, 64
+    x, _ = oracle.gh_rule(6)
+    dt = 0.3 / float(np.max(x))
+    kw = dict(n_low=3, eq_low=2, n_high=6, eq_high=4, kn=0.2, xbc=oracle.XBC_PRESSURE, rho_in=2.0,
+              rho_out=1.0, tau_mode=oracle.TAU_RHO, tile_w=tw)
+    G = lb.Lattice(lb.make_params(nx, ny, storage=storage, dt=dt, **kw))
+    O = oracle.Lattice(nx, ny, dt=dt, **kw)
+    xx = np.arange(nx)[None, :] * np.ones((ny + 1, 1))
+    rho = 2.0 - 1.0 * xx / (nx - 1)
+    for L in (G, O):
+        L.set_regions(8, 8)
+        L.init_equilibrium(rho, 0 * xx, 0 * xx)
+    return G, O
+
+
+def test_pressure_channel_regrid_fp64(oracle, lb):
+    # the C3 procedure at reduced size: every 100 steps the indicator picks
+    # per-tile bands (theta, clamp [4, 20]) and switched nodes are converted
+    G, O = _c3_small(oracle, lb, "f64", 100)
+    theta, bmin, bmax = 0.002, 4, 20
+    for _ in range(3):
+        O.step(100)
+        G.step(100)
+        Bo = O.indicator()
+        guard = np.abs(Bo - theta) <= 1e-9 * theta
+        assert guard.sum() == 0
+        lo, hi = O.bands_from_indicator(Bo, theta, bmin, bmax)
+        O.update_regions(lo, hi)
+        G.update_regions(theta, bmin, bmax)
+        glo, ghi = G.get_regions()
+        np.testing.assert_array_equal(glo, lo)
+        np.testing.assert_array_equal(ghi, hi)
+    _, uxo, uyo = O.moments()
+    _, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("bf16", 2e-3)])
+def test_pressure_channel_storage_error(oracle, lb, storage, tol):
+    # reduced-precision population storage (weight-shifted) against the FP64
+    # oracle on the same pressure-driven channel (fixed bands)
+    G, O = _c3_small(oracle, lb, storage, 0)
+    O.step(300)
+    G.step(300)
+    _, uxo, uyo = O.moments()
+    _, uxg, uyg = G.moments()
+    err = rel_u(uxg, uyg, uxo, uyo)
+    print(f"{storage}: relative velocity error vs FP64 oracle after 300 steps = {err:.3e}")
+    assert err < tol
