@@ -190,6 +190,54 @@ lb_status lb_autotune(lb_lattice *L, int32_t steps, int32_t rows_out[2]);
  * rows (interpolation mode only). */
 lb_status lb_region_counts(const lb_lattice *L, int64_t counts[3]);
 
+/* ---------------------------------------------------------------------
+ * Learned interface closure.  When low-order (D2Q9) populations are lifted
+ * to the high-order set (D2Q36, order 4), the non-equilibrium Hermite
+ * coefficients D2Q9 cannot carry are unknown (0 in the analytic
+ * projection).  A perceptron 10 -> 64 -> 64 -> 8 (tanh, tanh, linear)
+ * predicts the six of total order 3-4 -- (3,0), (0,3), (3,1), (1,3), (4,0),
+ * (0,4) -- plus two logits of a region flag (indicator above threshold).
+ * Inputs, from the node's D2Q9 populations: rho - 1, ux, uy, log Kn_loc and
+ * the non-equilibrium coefficients (2,0), (1,1), (0,2), (2,1), (1,2), (2,2)
+ * over rho; inputs and targets are standardised (norm = 10 input means,
+ * 10 input deviations, 6 target means, 6 target deviations).  Parameters
+ * are FP32, layout W1[64][10], b1[64], W2[64][64], b2[64], W3[8][64], b3[8].
+ * Training runs in FP32; inference in the lift uses bf16 weights.
+ * All pointers are device memory unless said otherwise. */
+int64_t lb_mlp_param_count(void);
+size_t lb_mlp_workspace_bytes(int64_t n);
+
+/* y[n][8] = network(x[n][10]) in FP32. */
+lb_status lb_mlp_forward(const float *params, const float *x, float *y, int64_t n, void *ws, void *hip_stream);
+
+/* Gradient of the batch mean of [squared error of the 6 regression outputs
+ * / 6 + cross-entropy of the 2 flag logits]; loss = that mean (device
+ * float).  Deterministic. */
+lb_status lb_mlp_loss_grad(const float *params, const float *x, const float *t, const int32_t *flag, int64_t n,
+                           float *grad, float *loss, void *ws, void *hip_stream);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected), step >= 1. */
+lb_status lb_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr,
+                      void *hip_stream);
+
+/* Closure coefficients (row-major 6x6 Hermite indices, zero outside the six
+ * predicted components) of n D2Q9 nodes given as FP64 absolute populations
+ * [n][9]; norm is a host array of 32 floats; bf16 weights.  Test hook. */
+lb_status lb_closure_eval(const float *params, const float *norm, double kn_ref, int32_t tau_rho, double rho_ref,
+                          const double *f9, int64_t n, double *c36, void *hip_stream);
+
+/* Training samples from a lattice whose listed nodes (j*nx + i) are in the
+ * D2Q36 set: raw (unstandardised) features of the node restricted to D2Q9
+ * x[n][10], raw targets t[n][6] (missing non-equilibrium coefficients over
+ * rho) and flag[n] (indicator above theta).  Asynchronous. */
+lb_status lb_closure_samples(lb_lattice *L, const int32_t *nodes, int64_t n, double theta, float *x, float *t,
+                             int32_t *flag);
+
+/* Use the network in every D2Q9 -> D2Q36 lift of this lattice (params
+ * device FP32, norm host [32]); params == NULL restores the analytic
+ * projection.  Waits. */
+lb_status lb_set_closure(lb_lattice *L, const float *params, const float *norm);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,12 @@ struct Inst {
     static void project_halo(const StepArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_project_halo<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
     }
+    static void closure_infer(const StepArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_closure_infer<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
+    }
+    static void closure_samples(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_closure_samples<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
+    }
     static void refresh(const NodeArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_refresh<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
     }
@@ -70,6 +76,8 @@ struct Inst {
         k.convert = &convert;
         k.paper_iface = &paper_iface;
         k.project = &project;
+        k.closure_infer = &closure_infer;
+        k.closure_samples = &closure_samples;
         k.update_kernel = reinterpret_cast<const void *>(&k_update<ST, S, O>);
         return k;
     }

@@ -41,6 +41,7 @@ struct Phys {
     double rho_in, rho_out;
     double gx, gy;
     double uw[4];      // bottom x, y, top x, y
+    double kn;         // Kn at rho_ref
     int32_t tau_mode;
     int32_t pad;
 };
@@ -56,6 +57,14 @@ struct SetK {
     float spf[2][36], wKf[2], wDf[2];
 };
 
+// Learned closure used by the lift (bf16 weights of the 10-64-64-8 network
+// and the standardisation constants) -- see lb_mlp.hip
+struct ClosureNorm {
+    float xmean[10], xstd[10], tmean[6], tstd[6];
+    float kn_ref;      // Kn at rho_ref (the input is log of the local Kn)
+    int32_t tau_rho;   // local Kn ~ 1/rho
+};
+
 struct StepArgs {
     Geo g;
     Phys ph;
@@ -67,6 +76,9 @@ struct StepArgs {
     int32_t nitems;      // work items (64 columns x a strip of rows)
     int32_t chunk;       // items per XCD slot (XCD-aware block mapping)
     const int32_t *items;   // device: 4 ints per item: i0, j0, j1, unused
+    float *clo;             // per lifted node: the 6 closure coefficients (NULL = analytic)
+    const uint16_t *clw;    // closure weights (bf16)
+    ClosureNorm cn;
 };
 
 // Arguments of the non-step kernels (one thread per node).
@@ -83,6 +95,11 @@ struct NodeArgs {
     double *out0, *out1, *out2;      // device FP64 outputs
     const int32_t *oblo, *obhi;      // previous bands (region change)
     const double *closure;           // optional closure coefficients (lift)
+    const int32_t *nodes;            // node list (samples)
+    int64_t nnodes;
+    double theta;
+    float *fx, *ft;                  // sample features / targets
+    int32_t *flag;
 };
 
 }  // namespace lbi

@@ -795,8 +795,20 @@ __global__ __launch_bounds__(128) void k_finish(const StepArgs A) {
 
 // One population t of the projection of a source node (set SS, absolute
 // values fs) onto set DD; also returns rho, u of the node.
+// order of the six components a tensor-product D2Q9 lacks at total order 3-4
+__device__ __forceinline__ int missing_index(int k, int m) {
+    if (k == 3 && m == 0) return 0;
+    if (k == 0 && m == 3) return 1;
+    if (k == 3 && m == 1) return 2;
+    if (k == 1 && m == 3) return 3;
+    if (k == 4 && m == 0) return 4;
+    if (k == 0 && m == 4) return 5;
+    return -1;
+}
+
 template <class SS, class DD>
-__device__ double project_one(const double *fs, int t, double &rho, double &ux, double &uy) {
+__device__ double project_one(const double *fs, int t, double &rho, double &ux, double &uy,
+                              const float *cl6 = nullptr) {
     using TS = typename SS::T;
     using TD = typename DD::T;
     constexpr int NS = SS::N, ND = DD::N;
@@ -843,7 +855,12 @@ __device__ double project_one(const double *fs, int t, double &rho, double &ux, 
             for (int m = 0; m < ND; ++m) {
                 double eqd = (k + m <= DD::EQ) ? rho * px[k] * py[m] : 0.0;
                 double neq = 0.0;
-                if (k < NM && m < NM) neq = a[k][m] - ((k + m <= SS::EQ) ? rho * px[k] * py[m] : 0.0);
+                if (k < NM && m < NM) {
+                    neq = a[k][m] - ((k + m <= SS::EQ) ? rho * px[k] * py[m] : 0.0);
+                } else if (cl6) {
+                    const int mi = missing_index(k, m);
+                    if (mi >= 0) neq = double(cl6[mi]);
+                }
                 b += (eqd + neq) * TD::hk.v[m][tq];
             }
             s += TD::hk.v[k][tp] * b;
@@ -914,7 +931,7 @@ __global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
         const int i = A.items[2 * e], j = A.items[2 * e + 1];
         double fs[LS::Q];
         load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, fs);
-        const double v = project_one<LS, HS>(fs, t, rho, ux, uy);
+        const double v = project_one<LS, HS>(fs, t, rho, ux, uy, A.clo ? A.clo + 6 * e : nullptr);
         emit_pop<ST, HS>(A.other, copy, i, j, A.rho_shift, t, v, rho, ux, uy, A.g, A.ph);
     } else if (k < n0 + n1) {
         const int e = int((k - n0) / LS::Q) + A.nitems, t = int((k - n0) % LS::Q);
@@ -923,6 +940,170 @@ __global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
         load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, fs);
         const double v = project_one<HS, LS>(fs, t, rho, ux, uy);
         emit_pop<ST, LS>(A.self, copy, i, j, A.rho_shift, t, v, rho, ux, uy, A.g, A.ph);
+    }
+}
+
+// ------------------------------------------------------- learned closure
+// Network 10 -> 64 -> 64 -> 8 (tanh, tanh, linear); parameter layout
+// W1[64][10], b1[64], W2[64][64], b2[64], W3[8][64], b3[8].
+constexpr int MLP_NIN = 10, MLP_NH = 64, MLP_NOUT = 8;
+constexpr int MLP_OFF_B1 = MLP_NH * MLP_NIN, MLP_OFF_W2 = MLP_OFF_B1 + MLP_NH;
+constexpr int MLP_OFF_B2 = MLP_OFF_W2 + MLP_NH * MLP_NH, MLP_OFF_W3 = MLP_OFF_B2 + MLP_NH;
+constexpr int MLP_OFF_B3 = MLP_OFF_W3 + MLP_NOUT * MLP_NH, MLP_NPARAM = MLP_OFF_B3 + MLP_NOUT;
+
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+__device__ __forceinline__ uint16_t f_to_bf16(float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+// Raw inputs of a D2Q9 node (absolute populations): rho - 1, ux, uy,
+// log Kn_loc, then (a_km - a_eq,km)/rho for (2,0),(1,1),(0,2),(2,1),(1,2),(2,2)
+// with the 2nd-order equilibrium (no components above order 2).
+template <class LS>
+__device__ void closure_features(const double *f9, double kn_loc, double &rho, float *x) {
+    using TL = typename LS::T;
+    double a[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int al = 0; al < 9; ++al) s += f9[al] * TL::he.v[k][al % 3] * TL::he.v[m][al / 3];
+            a[k][m] = s;
+        }
+    rho = a[0][0];
+    const double ux = a[1][0] / rho, uy = a[0][1] / rho;
+    x[0] = float(rho - 1.0);
+    x[1] = float(ux);
+    x[2] = float(uy);
+    x[3] = float(log(kn_loc));
+    x[4] = float((a[2][0] - rho * ux * ux) / rho);
+    x[5] = float((a[1][1] - rho * ux * uy) / rho);
+    x[6] = float((a[0][2] - rho * uy * uy) / rho);
+    x[7] = float(a[2][1] / rho);
+    x[8] = float(a[1][2] / rho);
+    x[9] = float(a[2][2] / rho);
+}
+
+// FP32 forward pass with bf16 weights (bits in w); x standardised in place
+template <class W>
+__device__ void mlp_forward_one(const W &w, const float *x, float *y) {
+    float h1[MLP_NH];
+#pragma unroll 4
+    for (int o = 0; o < MLP_NH; ++o) {
+        float s = w(MLP_OFF_B1 + o);
+#pragma unroll
+        for (int k = 0; k < MLP_NIN; ++k) s += w(o * MLP_NIN + k) * x[k];
+        h1[o] = tanhf(s);
+    }
+    float h2[MLP_NH];
+    for (int o = 0; o < MLP_NH; ++o) {
+        float s = w(MLP_OFF_B2 + o);
+#pragma unroll 8
+        for (int k = 0; k < MLP_NH; ++k) s += w(MLP_OFF_W2 + o * MLP_NH + k) * h1[k];
+        h2[o] = tanhf(s);
+    }
+#pragma unroll
+    for (int o = 0; o < MLP_NOUT; ++o) {
+        float s = w(MLP_OFF_B3 + o);
+#pragma unroll 8
+        for (int k = 0; k < MLP_NH; ++k) s += w(MLP_OFF_W3 + o * MLP_NH + k) * h2[k];
+        y[o] = s;
+    }
+}
+
+struct WBf16 {
+    const uint16_t *p;
+    __device__ float operator()(int i) const { return bf16_to_f(p[i]); }
+};
+
+// closure coefficients C_km of the six missing components for one D2Q9 node
+template <class LS, class W>
+__device__ void closure_coeffs(const W &w, const ClosureNorm &cn, const double *f9, double rho_ref, float *c6) {
+    float x[MLP_NIN], y[MLP_NOUT];
+    double rho;
+    // local Kn: Kn at rho_ref, scaled as 1/rho when the relaxation time is
+    double a00 = 0.0;
+#pragma unroll
+    for (int al = 0; al < 9; ++al) a00 += f9[al];
+    const double kn_loc = cn.tau_rho ? cn.kn_ref * rho_ref / a00 : cn.kn_ref;
+    closure_features<LS>(f9, kn_loc, rho, x);
+#pragma unroll
+    for (int k = 0; k < MLP_NIN; ++k) x[k] = (x[k] - cn.xmean[k]) / cn.xstd[k];
+    mlp_forward_one(w, x, y);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c6[k] = float(rho) * (cn.tmean[k] + cn.tstd[k] * y[k]);
+}
+
+// Per step, before the projection pass: closure coefficients of the lifted
+// nodes (the first A.nitems entries of the projection list, low set).
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_closure_infer(const StepArgs A) {
+    if constexpr (LS::N == 3 && HS::N == 6) {
+        const int e = blockIdx.x * blockDim.x + threadIdx.x;
+        if (e >= A.nitems) return;
+        const int i = A.items[2 * e], j = A.items[2 * e + 1];
+        double f9[9];
+        load_node_d<ST, LS>(A.self, A.cur ^ 1, i, j, A.rho_shift, f9);
+        float c6[6];
+        closure_coeffs<LS>(WBf16{A.clw}, A.cn, f9, A.ph.rho_ref, c6);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) A.clo[6 * e + k] = c6[k];
+    }
+}
+
+// Training samples from the high set of an all-high run: for each listed
+// node, raw features of its restriction to the low set, raw regression
+// targets (missing non-equilibrium coefficients / rho) and the flag
+// (indicator above theta).
+template <class ST, class HS, class LS>
+__global__ void k_closure_samples(const NodeArgs A) {
+    if constexpr (LS::N == 3 && HS::N == 6) {
+        const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (k >= A.nnodes) return;
+        const int n = A.nodes[k];
+        const int j = n / A.g.nx, i = n - j * A.g.nx;
+        using TH = typename HS::T;
+        double f36[36], f9[9];
+        load_node_d<ST, HS>(A.self, A.cur, i, j, A.rho_shift, f36);
+        project_d<HS, LS>(f36, f9, nullptr);
+        double a[6][6];
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk)
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+                if (kk > 4 || m > 4) continue;
+                double s = 0.0;
+#pragma unroll
+                for (int al = 0; al < 36; ++al) s += f36[al] * TH::he.v[kk][al % 6] * TH::he.v[m][al / 6];
+                a[kk][m] = s;
+            }
+        const double rho = a[0][0], ux = a[1][0] / rho, uy = a[0][1] / rho;
+        auto neq = [&](int kk, int m) {
+            double eq = 1.0;
+            for (int q = 0; q < kk; ++q) eq *= ux;
+            for (int q = 0; q < m; ++q) eq *= uy;
+            return (a[kk][m] - (kk + m <= HS::EQ ? rho * eq : 0.0)) / rho;
+        };
+        float *t = A.ft + 6 * k;
+        t[0] = float(neq(3, 0));
+        t[1] = float(neq(0, 3));
+        t[2] = float(neq(3, 1));
+        t[3] = float(neq(1, 3));
+        t[4] = float(neq(4, 0));
+        t[5] = float(neq(0, 4));
+        const double b = fmax(fabs(neq(2, 0)), fmax(fabs(neq(1, 1)), fabs(neq(0, 2))));
+        A.flag[k] = b > A.theta ? 1 : 0;
+        // local Kn: Kn at rho_ref, scaled as 1/rho when the relaxation time is
+        const double kn_loc = A.ph.tau_mode == TAU_RHO ? A.ph.kn * A.ph.rho_ref / rho : A.ph.kn;
+        double r9;
+        float x[MLP_NIN];
+        closure_features<LS>(f9, kn_loc, r9, x);
+#pragma unroll
+        for (int q = 0; q < MLP_NIN; ++q) A.fx[MLP_NIN * k + q] = x[q];
     }
 }
 

@@ -1,0 +1,216 @@
+// lb_mlp.hip -- kernels of the learned interface closure: FP32 training of
+// the 10-64-64-8 network (forward, loss, backward, Adam) and the bf16
+// closure evaluation used by the tests.
+//
+// Training is written as dense layers over a batch, one thread per output
+// element; every reduction over the batch runs in a fixed order inside one
+// thread, so gradients are deterministic.
+#include <hip/hip_runtime.h>
+
+#include "../../include/lb.h"
+#include "lb_kernels.hpp"
+#include "lb_registry.hpp"
+
+using namespace lbk;
+
+namespace {
+
+// out[r][c] = act(sum_k A[r][k] W[c][k] + b[c])
+__global__ void k_dense(const float *A, int K, const float *W, const float *b, float *out, int M, int64_t n,
+                        int act) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * M) return;
+    const int64_t r = idx / M;
+    const int c = int(idx % M);
+    float s = b ? b[c] : 0.0f;
+    for (int k = 0; k < K; ++k) s += A[r * K + k] * W[c * K + k];
+    out[idx] = act ? tanhf(s) : s;
+}
+
+// out[r][k] = (sum_c D[r][c] W[c][k]) (1 - H[r][k]^2): back through a
+// tanh layer
+__global__ void k_dense_back(const float *D, int M, const float *W, const float *H, float *out, int K, int64_t n) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * K) return;
+    const int64_t r = idx / K;
+    const int k = int(idx % K);
+    float s = 0.0f;
+    for (int c = 0; c < M; ++c) s += D[r * M + c] * W[c * K + k];
+    const float h = H[idx];
+    out[idx] = s * (1.0f - h * h);
+}
+
+// gW[c][k] = sum_r D[r][c] H[r][k], gb[c] = sum_r D[r][c]
+__global__ void k_outer(const float *D, int M, const float *H, int K, int64_t n, float *gW, float *gb) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < M * K) {
+        const int c = idx / K, k = idx % K;
+        float s = 0.0f;
+        for (int64_t r = 0; r < n; ++r) s += D[r * M + c] * H[r * K + k];
+        gW[idx] = s;
+    } else if (idx < M * K + M) {
+        const int c = idx - M * K;
+        float s = 0.0f;
+        for (int64_t r = 0; r < n; ++r) s += D[r * M + c];
+        gb[c] = s;
+    }
+}
+
+// per sample: squared error of the 6 regression outputs / 6 + cross-entropy
+// of the 2 flag logits; dY = gradient of the batch mean
+__global__ void k_loss(const float *Y, const float *T, const int32_t *flag, int64_t n, float *dY, float *lv) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const float *y = Y + 8 * r;
+    float *d = dY + 8 * r;
+    float l = 0.0f;
+    for (int c = 0; c < 6; ++c) {
+        const float e = y[c] - T[6 * r + c];
+        l += e * e / 6.0f;
+        d[c] = 2.0f * e / 6.0f / float(n);
+    }
+    const float z0 = y[6], z1 = y[7], zm = fmaxf(z0, z1);
+    const float lse = zm + logf(expf(z0 - zm) + expf(z1 - zm));
+    const int f = flag[r];
+    l += lse - (f ? z1 : z0);
+    d[6] = (expf(z0 - lse) - (f == 0 ? 1.0f : 0.0f)) / float(n);
+    d[7] = (expf(z1 - lse) - (f == 1 ? 1.0f : 0.0f)) / float(n);
+    lv[r] = l;
+}
+
+__global__ void k_mean1(const float *v, int64_t n, float *out) {
+    __shared__ float sh[256];
+    float s = 0.0f;
+    for (int64_t k = threadIdx.x; k < n; k += 256) s += v[k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0] / float(n);
+}
+
+__global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t np, float lr, float bc1, float bc2) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const float gk = g[k];
+    const float mk = 0.9f * m[k] + 0.1f * gk;
+    const float vk = 0.999f * v[k] + 0.001f * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    p[k] -= lr * (mk / bc1) / (sqrtf(vk / bc2) + 1e-8f);
+}
+
+__global__ void k_to_bf16(const float *p, uint16_t *out, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = f_to_bf16(p[k]);
+}
+
+// FP32 weights read through bf16 rounding: the inference precision
+struct WRound {
+    const float *p;
+    __device__ float operator()(int i) const { return bf16_to_f(f_to_bf16(p[i])); }
+};
+
+__global__ void k_closure_eval(const float *params, ClosureNorm cn, const double *f9, int64_t n, double *c36,
+                               double rho_ref) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double f[9];
+    for (int a = 0; a < 9; ++a) f[a] = f9[9 * k + a];
+    float c6[6];
+    closure_coeffs<lbt::VSet<3, 2>>(WRound{params}, cn, f, rho_ref, c6);
+    double *o = c36 + 36 * k;
+    for (int a = 0; a < 36; ++a) o[a] = 0.0;
+    o[3 * 6 + 0] = c6[0];
+    o[0 * 6 + 3] = c6[1];
+    o[3 * 6 + 1] = c6[2];
+    o[1 * 6 + 3] = c6[3];
+    o[4 * 6 + 0] = c6[4];
+    o[0 * 6 + 4] = c6[5];
+}
+
+int blocks(int64_t n, int t = 256) { return int((n + t - 1) / t); }
+
+}  // namespace
+
+namespace lbk {
+void launch_to_bf16(const float *p, uint16_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(blocks(MLP_NPARAM)), dim3(256), 0, s, p, out, MLP_NPARAM);
+}
+}  // namespace lbk
+
+extern "C" {
+
+int64_t lb_mlp_param_count(void) { return MLP_NPARAM; }
+
+size_t lb_mlp_workspace_bytes(int64_t n) { return size_t(n > 0 ? n : 0) * 273 * 4 + 256; }
+
+lb_status lb_mlp_forward(const float *params, const float *x, float *y, int64_t n, void *ws, void *stream) {
+    if (!params || !x || !y || !ws || n < 0) return lb_internal_fail(LB_EINVAL, "bad argument");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float *H1 = reinterpret_cast<float *>(ws), *H2 = H1 + n * 64;
+    const float *W1 = params, *b1 = params + MLP_OFF_B1, *W2 = params + MLP_OFF_W2, *b2 = params + MLP_OFF_B2;
+    const float *W3 = params + MLP_OFF_W3, *b3 = params + MLP_OFF_B3;
+    if (n == 0) return LB_OK;
+    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 64)), dim3(256), 0, s, x, 10, W1, b1, H1, 64, n, 1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 64)), dim3(256), 0, s, H1, 64, W2, b2, H2, 64, n, 1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 8)), dim3(256), 0, s, H2, 64, W3, b3, y, 8, n, 0);
+    return hipGetLastError() == hipSuccess ? LB_OK : lb_internal_fail(LB_EDEVICE, "mlp forward launch failed");
+}
+
+lb_status lb_mlp_loss_grad(const float *params, const float *x, const float *t, const int32_t *flag, int64_t n,
+                           float *grad, float *loss, void *ws, void *stream) {
+    if (!params || !x || !t || !flag || !grad || !loss || !ws || n <= 0)
+        return lb_internal_fail(LB_EINVAL, "bad argument");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    float *H1 = reinterpret_cast<float *>(ws), *H2 = H1 + n * 64, *Y = H2 + n * 64, *dY = Y + n * 8;
+    float *dZ2 = dY + n * 8, *dZ1 = dZ2 + n * 64, *lv = dZ1 + n * 64;
+    const float *W1 = params, *b1 = params + MLP_OFF_B1, *W2 = params + MLP_OFF_W2, *b2 = params + MLP_OFF_B2;
+    const float *W3 = params + MLP_OFF_W3, *b3 = params + MLP_OFF_B3;
+    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 64)), dim3(256), 0, s, x, 10, W1, b1, H1, 64, n, 1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 64)), dim3(256), 0, s, H1, 64, W2, b2, H2, 64, n, 1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 8)), dim3(256), 0, s, H2, 64, W3, b3, Y, 8, n, 0);
+    hipLaunchKernelGGL(k_loss, dim3(blocks(n)), dim3(256), 0, s, Y, t, flag, n, dY, lv);
+    hipLaunchKernelGGL(k_outer, dim3(blocks(8 * 64 + 8)), dim3(256), 0, s, dY, 8, H2, 64, n, grad + MLP_OFF_W3,
+                       grad + MLP_OFF_B3);
+    hipLaunchKernelGGL(k_dense_back, dim3(blocks(n * 64)), dim3(256), 0, s, dY, 8, W3, H2, dZ2, 64, n);
+    hipLaunchKernelGGL(k_outer, dim3(blocks(64 * 64 + 64)), dim3(256), 0, s, dZ2, 64, H1, 64, n, grad + MLP_OFF_W2,
+                       grad + MLP_OFF_B2);
+    hipLaunchKernelGGL(k_dense_back, dim3(blocks(n * 64)), dim3(256), 0, s, dZ2, 64, W2, H1, dZ1, 64, n);
+    hipLaunchKernelGGL(k_outer, dim3(blocks(64 * 10 + 64)), dim3(256), 0, s, dZ1, 64, x, 10, n, grad,
+                       grad + MLP_OFF_B1);
+    hipLaunchKernelGGL(k_mean1, dim3(1), dim3(256), 0, s, lv, n, loss);
+    return hipGetLastError() == hipSuccess ? LB_OK : lb_internal_fail(LB_EDEVICE, "mlp gradient launch failed");
+}
+
+lb_status lb_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr, void *stream) {
+    if (!params || !grad || !m || !v || step < 1) return lb_internal_fail(LB_EINVAL, "bad argument");
+    const float bc1 = 1.0f - powf(0.9f, float(step)), bc2 = 1.0f - powf(0.999f, float(step));
+    hipLaunchKernelGGL(k_adam, dim3(blocks(MLP_NPARAM)), dim3(256), 0, reinterpret_cast<hipStream_t>(stream), params,
+                       grad, m, v, int64_t(MLP_NPARAM), lr, bc1, bc2);
+    return hipGetLastError() == hipSuccess ? LB_OK : lb_internal_fail(LB_EDEVICE, "adam launch failed");
+}
+
+lb_status lb_closure_eval(const float *params, const float *norm, double kn_ref, int32_t tau_rho, double rho_ref,
+                          const double *f9, int64_t n, double *c36, void *stream) {
+    if (!params || !norm || !f9 || !c36 || n < 0) return lb_internal_fail(LB_EINVAL, "bad argument");
+    lbi::ClosureNorm cn{};
+    for (int k = 0; k < 10; ++k) {
+        cn.xmean[k] = norm[k];
+        cn.xstd[k] = norm[10 + k];
+    }
+    for (int k = 0; k < 6; ++k) {
+        cn.tmean[k] = norm[20 + k];
+        cn.tstd[k] = norm[26 + k];
+    }
+    cn.kn_ref = float(kn_ref);
+    cn.tau_rho = tau_rho;
+    if (n == 0) return LB_OK;
+    hipLaunchKernelGGL(k_closure_eval, dim3(blocks(n, 64)), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), params,
+                       cn, f9, n, c36, rho_ref);
+    return hipGetLastError() == hipSuccess ? LB_OK : lb_internal_fail(LB_EDEVICE, "closure launch failed");
+}
+
+}  // extern "C"

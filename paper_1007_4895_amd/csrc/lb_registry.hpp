@@ -25,6 +25,8 @@ struct KernelSet {
     NodeFn refresh, init_eq, set_pop, get_pop, moments, indicator, convert;
     IfaceFn paper_iface;   // valid when `self` is the low set of the pair
     ProjFn project;        // FP64 projection self -> partner
+    StepFn closure_infer;   // learned-closure inference of the lifted nodes (self = low set)
+    NodeFn closure_samples; // training samples from an all-high run (self = high set)
     const void *update_kernel;   // the __global__ symbol (for attribute queries)
 };
 
@@ -32,6 +34,13 @@ struct Registry {
     const KernelSet *sets;
     int count;
 };
+
+// error reporting shared by the runtime's translation units
+}  // namespace lbk
+#include "../../include/lb.h"
+lb_status lb_internal_fail(lb_status s, const char *msg);
+namespace lbk {
+void launch_to_bf16(const float *p, uint16_t *out, hipStream_t s);
 
 Registry registry_f64();
 Registry registry_f32();

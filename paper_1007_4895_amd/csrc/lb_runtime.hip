@@ -75,7 +75,7 @@ struct Layout {
     int64_t plane[2];
     size_t off_pop[2][2];   // [set][copy]
     size_t off_blo, off_bhi, off_oblo, off_obhi;
-    size_t off_items[2], off_fin, off_proj, off_stage, off_mom, off_part;
+    size_t off_items[2], off_fin, off_proj, off_stage, off_mom, off_part, off_clw, off_clo;
     int maxitems, maxfin;
     size_t stage_elems;
     size_t total;
@@ -123,6 +123,8 @@ Layout ws_layout(const lb_params &p) {
     L.off_stage = off; off = align_up(off + 8 * L.stage_elems, 256);
     L.off_mom = off; off = align_up(off + 8 * 3 * nodes, 256);
     L.off_part = off; off = align_up(off + 8 * 3 * 1024, 256);
+    L.off_clw = off; off = align_up(off + 2 * 5384, 256);
+    L.off_clo = off; off = align_up(off + 4 * 6 * nodes, 256);
     L.total = off;
     return L;
 }
@@ -284,6 +286,10 @@ struct lb_lattice {
     size_t ev_used;
     std::vector<int> ev_kind;   // per event pair: 1 = dominant update kernel, 0 = other update
     int64_t count[3];           // nodes per region: low, high, interface rows
+    bool closure_on;            // learned closure in the lift
+    uint16_t *d_clw;            // closure weights (bf16)
+    float *d_clo;               // closure coefficients of the lifted nodes
+    ClosureNorm cn;
     int dom;                    // set whose update moves the most bytes per step
 };
 
@@ -554,6 +560,13 @@ lb_status one_step(lb_lattice *L) {
         a.items = L->d_proj;
         a.nitems = L->nproj[0];
         a.chunk = L->nproj[1];
+        a.clo = nullptr;
+        if (L->closure_on && L->nproj[0]) {
+            a.clo = L->d_clo;
+            a.clw = L->d_clw;
+            a.cn = L->cn;
+            L->ks[0]->closure_infer(a, (L->nproj[0] + 127) / 128, L->stream);
+        }
         const int64_t nt = int64_t(L->nproj[0]) * L->Q[1] + int64_t(L->nproj[1]) * L->Q[0];
         L->ks[0]->project_halo(a, int((nt + 127) / 128), L->stream);
     }
@@ -570,6 +583,8 @@ lb_status one_step(lb_lattice *L) {
 }
 
 }  // namespace
+
+lb_status lb_internal_fail(lb_status s, const char *msg) { return fail(s, "%s", msg); }
 
 extern "C" {
 
@@ -696,6 +711,7 @@ lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t byte
     L->ph.gy = p->gy;
     for (int k = 0; k < 4; ++k) L->ph.uw[k] = p->u_wall[k];
     L->ph.tau_mode = p->tau_mode;
+    L->ph.kn = p->kn;
     L->d_blo = reinterpret_cast<int32_t *>(L->ws + lay.off_blo);
     L->d_bhi = reinterpret_cast<int32_t *>(L->ws + lay.off_bhi);
     L->d_oblo = reinterpret_cast<int32_t *>(L->ws + lay.off_oblo);
@@ -706,6 +722,8 @@ lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t byte
     L->d_stage = reinterpret_cast<double *>(L->ws + lay.off_stage);
     L->d_mom = reinterpret_cast<double *>(L->ws + lay.off_mom);
     L->d_part = reinterpret_cast<double *>(L->ws + lay.off_part);
+    L->d_clw = reinterpret_cast<uint16_t *>(L->ws + lay.off_clw);
+    L->d_clo = reinterpret_cast<float *>(L->ws + lay.off_clo);
     L->strip[0] = L->strip[1] = 0;
     L->order[0] = L->order[1] = 0;
     L->cur = 0;
@@ -1047,6 +1065,49 @@ lb_status lb_project(int32_t ns, int32_t eqs, int32_t nd, int32_t eqd, const dou
     const lbk::KernelSet *k = find_any(ns, eqs, nd, eqd);
     if (!k) return fail(LB_EUNSUPPORTED, "no projection kernel for this pair");
     k->project(f_src, closure, f_dst, n, reinterpret_cast<hipStream_t>(hip_stream));
+    HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_set_closure(lb_lattice *L, const float *params, const float *norm) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    if (!params) {
+        L->closure_on = false;
+        return LB_OK;
+    }
+    if (!norm) return fail(LB_EINVAL, "closure needs its standardisation constants");
+    if (L->n[0] != 3 || L->n[1] != 6 || L->eq[1] != 4)
+        return fail(LB_EUNSUPPORTED, "the learned closure is built for D2Q9 lifted to D2Q36 (order 4)");
+    for (int k = 0; k < 10; ++k) {
+        L->cn.xmean[k] = norm[k];
+        L->cn.xstd[k] = norm[10 + k];
+    }
+    for (int k = 0; k < 6; ++k) {
+        L->cn.tmean[k] = norm[20 + k];
+        L->cn.tstd[k] = norm[26 + k];
+    }
+    L->cn.kn_ref = float(L->p.kn);
+    L->cn.tau_rho = L->p.tau_mode == LB_TAU_RHO;
+    lbk::launch_to_bf16(params, L->d_clw, L->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(L->stream));
+    L->closure_on = true;
+    return LB_OK;
+}
+
+lb_status lb_closure_samples(lb_lattice *L, const int32_t *nodes, int64_t n, double theta, float *x, float *t,
+                             int32_t *flag) {
+    if (!L || !nodes || !x || !t || !flag || n < 0) return fail(LB_EINVAL, "bad argument");
+    if (!L->initialized) return fail(LB_ESTATE, "lattice not initialised");
+    if (L->n[0] != 3 || L->n[1] != 6) return fail(LB_EUNSUPPORTED, "samples are drawn for the D2Q9/D2Q36 pair");
+    NodeArgs a = node_args(L, 1, L->cur);
+    a.nodes = nodes;
+    a.nnodes = n;
+    a.theta = theta;
+    a.fx = x;
+    a.ft = t;
+    a.flag = flag;
+    if (n) L->ks[1]->closure_samples(a, int((n + 63) / 64), L->stream);
     HIPCHK(hipGetLastError());
     return LB_OK;
 }

@@ -87,6 +87,15 @@ def lib():
             "lb_region_counts": (C.c_int, [_vp, C.POINTER(C.c_int64)]),
             "lb_get_strip_rows": (C.c_int, [_vp, _ip]),
             "lb_autotune": (C.c_int, [_vp, C.c_int32, _ip]),
+            "lb_mlp_param_count": (C.c_int64, []),
+            "lb_mlp_workspace_bytes": (C.c_size_t, [C.c_int64]),
+            "lb_mlp_forward": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp]),
+            "lb_mlp_loss_grad": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, _vp, _vp, _vp, _vp]),
+            "lb_mlp_adam": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, C.c_float, _vp]),
+            "lb_closure_eval": (C.c_int, [_vp, C.POINTER(C.c_float), C.c_double, C.c_int32, C.c_double, _vp,
+                                          C.c_int64, _vp, _vp]),
+            "lb_closure_samples": (C.c_int, [_vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp]),
+            "lb_set_closure": (C.c_int, [_vp, _vp, C.POINTER(C.c_float)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -273,6 +282,112 @@ class Lattice:
         nh, na = C.c_int64(), C.c_int64()
         _check(lib().lb_kernel_times(self._h, C.byref(mh), C.byref(nh), C.byref(ma), C.byref(na)))
         return mh.value, nh.value, ma.value, na.value
+
+    # ------------------------------------------------------ learned closure
+    def set_closure(self, params=None, norm=None):
+        """Use the network (device float32 tensor of MLP_NPARAM values, norm =
+        32 standardisation constants) in every D2Q9 -> D2Q36 lift; None
+        restores the analytic projection."""
+        if params is None:
+            _check(lib().lb_set_closure(self._h, None, None))
+            return
+        nm = _norm(norm)
+        _check(lib().lb_set_closure(self._h, _vp(params.data_ptr()), nm.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def closure_samples(self, nodes, theta):
+        """Training samples at the listed nodes (device int32 tensor of
+        j * nx + i) of the D2Q36 set: raw features [n, 10], raw targets
+        [n, 6], flags [n] (device tensors, asynchronous)."""
+        import torch
+
+        n = nodes.numel()
+        x = torch.empty((n, MLP_NIN), dtype=torch.float32, device=self.device)
+        t = torch.empty((n, MLP_NREG), dtype=torch.float32, device=self.device)
+        f = torch.empty((n,), dtype=torch.int32, device=self.device)
+        _check(lib().lb_closure_samples(self._h, _vp(nodes.data_ptr()), n, theta, _vp(x.data_ptr()),
+                                        _vp(t.data_ptr()), _vp(f.data_ptr())))
+        return x, t, f
+
+
+MLP_NIN, MLP_NH, MLP_NOUT, MLP_NREG = 10, 64, 8, 6
+
+
+def _norm(norm):
+    nm = np.ascontiguousarray(np.asarray(norm, dtype=np.float32).ravel())
+    if nm.size != 32:
+        raise ValueError("closure standardisation needs 32 values")
+    return nm
+
+
+def _stream(t, stream):
+    import torch
+
+    st = stream if stream is not None else torch.cuda.current_stream(t.device)
+    return _vp(st.cuda_stream)
+
+
+def mlp_param_count():
+    return int(lib().lb_mlp_param_count())
+
+
+class MLP:
+    """Device FP32 training of the closure network through the C ABI (params,
+    gradients and Adam moments are torch float32 tensors on one device)."""
+
+    def __init__(self, params, max_batch, stream=None):
+        import torch
+
+        if params.numel() != mlp_param_count() or params.dtype != torch.float32:
+            raise ValueError("params must be a float32 tensor of mlp_param_count() values")
+        self.params = params.contiguous()
+        self.grad = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        self.max_batch = max_batch
+        self.ws = torch.empty(lib().lb_mlp_workspace_bytes(max_batch), dtype=torch.uint8, device=params.device)
+        self.t = 0
+        self.stream = stream
+
+    def forward(self, x):
+        import torch
+
+        n = x.shape[0]
+        if n > self.max_batch:
+            raise ValueError("batch larger than the workspace")
+        y = torch.empty((n, MLP_NOUT), dtype=torch.float32, device=x.device)
+        _check(lib().lb_mlp_forward(_vp(self.params.data_ptr()), _vp(x.data_ptr()), _vp(y.data_ptr()), n,
+                                    _vp(self.ws.data_ptr()), _stream(x, self.stream)))
+        return y
+
+    def loss_grad(self, x, t, flag):
+        n = x.shape[0]
+        if n > self.max_batch:
+            raise ValueError("batch larger than the workspace")
+        _check(lib().lb_mlp_loss_grad(_vp(self.params.data_ptr()), _vp(x.data_ptr()), _vp(t.data_ptr()),
+                                      _vp(flag.data_ptr()), n, _vp(self.grad.data_ptr()),
+                                      _vp(self.loss.data_ptr()), _vp(self.ws.data_ptr()),
+                                      _stream(x, self.stream)))
+        return self.loss, self.grad
+
+    def adam(self, lr):
+        self.t += 1
+        _check(lib().lb_mlp_adam(_vp(self.params.data_ptr()), _vp(self.grad.data_ptr()), _vp(self.m.data_ptr()),
+                                 _vp(self.v.data_ptr()), self.t, lr, _stream(self.params, self.stream)))
+
+
+def closure_eval(params, norm, kn_ref, tau_rho, rho_ref, f9, stream=None):
+    """Closure coefficients [n, 36] of D2Q9 nodes f9 [n, 9] (float64 device
+    tensor), network weights read through bf16 rounding."""
+    import torch
+
+    n = f9.shape[0]
+    out = torch.empty((n, 36), dtype=torch.float64, device=f9.device)
+    nm = _norm(norm)
+    _check(lib().lb_closure_eval(_vp(params.data_ptr()), nm.ctypes.data_as(C.POINTER(C.c_float)), kn_ref,
+                                 1 if tau_rho else 0, rho_ref, _vp(f9.data_ptr()), n, _vp(out.data_ptr()),
+                                 _stream(f9, stream)))
+    return out
 
 
 def project(ns, eqs, nd, eqd, f_src, f_dst, closure=None, stream=None):
