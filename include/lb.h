@@ -229,7 +229,8 @@ lb_status lb_closure_eval(const float *params, const float *norm, double kn_ref,
 /* Training samples from a lattice whose listed nodes (j*nx + i) are in the
  * D2Q36 set: raw (unstandardised) features of the node restricted to D2Q9
  * x[n][10], raw targets t[n][6] (missing non-equilibrium coefficients over
- * rho) and flag[n] (indicator above theta).  Asynchronous. */
+ * rho) and flag[n] (indicator above theta).  A listed index outside the
+ * lattice gets NaN features and targets and flag -1.  Asynchronous. */
 lb_status lb_closure_samples(lb_lattice *L, const int32_t *nodes, int64_t n, double theta, float *x, float *t,
                              int32_t *flag);
 

@@ -1065,6 +1065,12 @@ __global__ void k_closure_samples(const NodeArgs A) {
         const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         if (k >= A.nnodes) return;
         const int n = A.nodes[k];
+        if (n < 0 || n >= A.g.nx * A.g.nrow) {   // not a node: marked, nothing read
+            for (int q = 0; q < MLP_NIN; ++q) A.fx[MLP_NIN * k + q] = __builtin_nanf("");
+            for (int q = 0; q < 6; ++q) A.ft[6 * k + q] = __builtin_nanf("");
+            A.flag[k] = -1;
+            return;
+        }
         const int j = n / A.g.nx, i = n - j * A.g.nx;
         using TH = typename HS::T;
         double f36[36], f9[9];
