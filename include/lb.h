@@ -239,6 +239,43 @@ lb_status lb_closure_samples(lb_lattice *L, const int32_t *nodes, int64_t n, dou
  * projection.  Waits. */
 lb_status lb_set_closure(lb_lattice *L, const float *params, const float *norm);
 
+/* ---------------------------------------------------------------------
+ * Batches: many independent lattices (channels of different size, Kn and
+ * velocity-set pair) advanced together.  Each step issues, per velocity-set
+ * pair present, one launch per kernel (update of each set, interface
+ * projection, finish) covering the work items of every lattice of that
+ * pair, instead of one launch per kernel per lattice; with a graph segment
+ * set, runs of that many steps are captured once into a HIP graph and
+ * replayed.  Every step of every lattice is the same computation as
+ * lb_step (bit-identical results).
+ *
+ * The lattices stay owned by the caller and must outlive the batch; they
+ * must share a storage type, use the Hermite interface, have no learned
+ * closure set and be at the same copy parity (same step count modulo 2).
+ * A lattice stepped on its own in between makes lb_batch_step fail with
+ * LB_ESTATE; region changes are picked up (the work lists are rebuilt).
+ * The batch allocates its descriptor table and work lists with hipMalloc.
+ * hip_stream must be a created stream (not the null stream) for graphs; the
+ * batch orders itself after and before the lattices' own streams. */
+typedef struct lb_batch lb_batch;
+
+lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stream, lb_batch **out);
+void lb_batch_destroy(lb_batch *B);
+
+/* Steps per captured graph (0 = direct launches, the default).  Asynchronous
+ * otherwise, like lb_step. */
+lb_status lb_batch_set_graph(lb_batch *B, int32_t segment_steps);
+lb_status lb_batch_step(lb_batch *B, int64_t steps);
+
+/* Rows per work item of the low / high sets (0 = automatic), and the
+ * autotuner that times candidates for `steps` steps each and keeps the
+ * fastest (lattice states are restored). */
+lb_status lb_batch_set_strip_rows(lb_batch *B, int32_t rows_low, int32_t rows_high);
+lb_status lb_batch_autotune(lb_batch *B, int32_t steps, int32_t rows_out[2]);
+
+/* Total nodes, kernel launches per step, velocity-set pairs present. */
+lb_status lb_batch_info(const lb_batch *B, int64_t *nodes, int32_t *launches_per_step, int32_t *kinds);
+
 #ifdef __cplusplus
 }
 #endif

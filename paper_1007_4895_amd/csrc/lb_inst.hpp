@@ -28,6 +28,15 @@ struct Inst {
     static void closure_samples(const NodeArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_closure_samples<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
     }
+    static void update_batch(const BatchArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_update_batch<ST, S, O>), dim3(grid), dim3(64 * update_split<S>()), 0, s, a);
+    }
+    static void finish_batch(const BatchArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_finish_batch<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
+    }
+    static void project_batch(const BatchArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_project_halo_batch<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
+    }
     static void refresh(const NodeArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_refresh<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
     }
@@ -78,6 +87,9 @@ struct Inst {
         k.project = &project;
         k.closure_infer = &closure_infer;
         k.closure_samples = &closure_samples;
+        k.update_batch = &update_batch;
+        k.finish_batch = &finish_batch;
+        k.project_batch = &project_batch;
         k.update_kernel = reinterpret_cast<const void *>(&k_update<ST, S, O>);
         return k;
     }

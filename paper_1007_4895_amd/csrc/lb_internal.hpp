@@ -81,6 +81,17 @@ struct StepArgs {
     ClosureNorm cn;
 };
 
+// A batch of independent lattices stepped together: per-lattice arguments
+// in device memory, one merged item list per kernel.
+struct BatchArgs {
+    const StepArgs *desc;   // device: per lattice, the StepArgs of this kernel's set
+    const int32_t *items;   // device: 4 ints per item, the last names the lattice
+    int32_t nitems;         // items (projection: entries projecting up)
+    int32_t chunk;          // update: items per XCD slot
+    int32_t cur;            // source copy of every lattice
+    int32_t nsplit;         // projection: entries projecting down
+};
+
 // Arguments of the non-step kernels (one thread per node).
 struct NodeArgs {
     Geo g;

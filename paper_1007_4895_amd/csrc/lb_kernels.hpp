@@ -442,14 +442,32 @@ template <class SS>
 constexpr int update_waves() { return SS::Q == 36 ? 4 : SS::Q == 16 ? 4 : 6; }
 
 template <class ST, class SS, class OO, int WV>
-__device__ __forceinline__ void update_rows(const StepArgs &A, const int i0, const int j0, const int j1,
-                                            const int lane);
+__device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const int i0, const int j0,
+                                            const int j1, const int lane);
+
+// one work item (64 columns x rows j0..j1) of one lattice
+template <class ST, class SS, class OO>
+__device__ __forceinline__ void update_item(const StepArgs &A, const int cur, const int i0, const int j0,
+                                            const int j1) {
+    constexpr int SPLIT = update_split<SS>();
+    const int lane = threadIdx.x & 63;
+    // the wave index is wave-uniform: each wave runs the row loop compiled
+    // for its own abscissae, so every population's upwind direction and
+    // constants are known at compile time
+    const int wv = SPLIT > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6) : 0;
+    if (wv == 0) update_rows<ST, SS, OO, 0>(A, cur, i0, j0, j1, lane);
+    if constexpr (SPLIT > 1) {
+        if (wv == 1) update_rows<ST, SS, OO, 1>(A, cur, i0, j0, j1, lane);
+    }
+    if constexpr (SPLIT > 2) {
+        if (wv == 2) update_rows<ST, SS, OO, 2>(A, cur, i0, j0, j1, lane);
+    }
+}
 
 template <class ST, class SS, class OO>
 __global__ __launch_bounds__(64 * update_split<SS>())
 __attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : update_waves<SS>())))
 void k_update(const StepArgs A) {
-    constexpr int SPLIT = update_split<SS>();
     // XCD-aware mapping: consecutive items (neighbouring strips) go to
     // blocks that the dispatcher places on the same XCD (block b -> XCD b % 8)
     const int b = blockIdx.x;
@@ -457,23 +475,28 @@ void k_update(const StepArgs A) {
     if (it >= A.nitems) return;
     const int i0 = A.items[4 * it], j0 = A.items[4 * it + 1], j1 = A.items[4 * it + 2];
     if (j0 >= j1) return;   // padding item
-    const int lane = threadIdx.x & 63;
-    // the wave index is wave-uniform: each wave runs the row loop compiled
-    // for its own abscissae, so every population's upwind direction and
-    // constants are known at compile time
-    const int wv = SPLIT > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6) : 0;
-    if (wv == 0) update_rows<ST, SS, OO, 0>(A, i0, j0, j1, lane);
-    if constexpr (SPLIT > 1) {
-        if (wv == 1) update_rows<ST, SS, OO, 1>(A, i0, j0, j1, lane);
-    }
-    if constexpr (SPLIT > 2) {
-        if (wv == 2) update_rows<ST, SS, OO, 2>(A, i0, j0, j1, lane);
-    }
+    update_item<ST, SS, OO>(A, A.cur, i0, j0, j1);
+}
+
+// The same update for a batch of independent lattices in one launch: item
+// (i0, j0, j1, l) belongs to lattice l, whose arguments are B.desc[l]; the
+// lattices of a batch step together, so the copy parity is the launch's.
+template <class ST, class SS, class OO>
+__global__ __launch_bounds__(64 * update_split<SS>())
+__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : update_waves<SS>())))
+void k_update_batch(const BatchArgs B) {
+    const int b = blockIdx.x;
+    const int it = (b & 7) * B.chunk + (b >> 3);
+    if (it >= B.nitems) return;
+    const int i0 = B.items[4 * it], j0 = B.items[4 * it + 1], j1 = B.items[4 * it + 2];
+    const int l = B.items[4 * it + 3];
+    if (j0 >= j1) return;   // padding item
+    update_item<ST, SS, OO>(B.desc[l], B.cur, i0, j0, j1);
 }
 
 template <class ST, class SS, class OO, int WV>
-__device__ __forceinline__ void update_rows(const StepArgs &A, const int i0, const int j0, const int j1,
-                                            const int lane) {
+__device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const int i0, const int j0,
+                                            const int j1, const int lane) {
     using T = typename ST::M;
     using SV = typename ST::S;
     using TB = typename SS::T;
@@ -500,9 +523,9 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int i0, con
     const int64_t rb = A.self.rowbase - 2;
     const unsigned nbytes = unsigned(int64_t(Q) * P * EB);
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void *)A.self.base[A.cur], 0, int(nbytes), 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)A.self.base[cur], 0, int(nbytes), 0x00020000);
     const __amdgpu_buffer_rsrc_t rd =
-        __builtin_amdgcn_make_buffer_rsrc((void *)A.self.base[A.cur ^ 1], 0, int(nbytes), 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc((void *)A.self.base[cur ^ 1], 0, int(nbytes), 0x00020000);
     const unsigned OOB = nbytes;
     const unsigned vl = unsigned(min(max(col, -2), nx + 1) + 2) * EB;
 #define LB_SOFF(a, j) unsigned(((int64_t)(a) * P + rb + (int64_t)((j) + 2) * pitch) * EB)
@@ -777,11 +800,9 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int i0, con
 // Row images (periodic y) and pressure columns of the nodes listed in
 // A.items (i, j, set, 0): node-local, from the freshly written copy.
 template <class ST, class LS, class HS>
-__global__ __launch_bounds__(128) void k_finish(const StepArgs A) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.nitems) return;
-    const int i = A.items[4 * k], j = A.items[4 * k + 1], set = A.items[4 * k + 2];
-    const int copy = A.cur ^ 1;
+__device__ __forceinline__ void finish_item(const StepArgs &A, const int cur, const int i, const int j,
+                                            const int set) {
+    const int copy = cur ^ 1;
     if (set == 0) {
         double f[LS::Q];
         load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, f);
@@ -791,6 +812,22 @@ __global__ __launch_bounds__(128) void k_finish(const StepArgs A) {
         load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, f);
         emit_node<ST, HS>(A.other, copy, i, j, A.rho_shift, f, false, A.g, A.ph);
     }
+}
+
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_finish(const StepArgs A) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.nitems) return;
+    finish_item<ST, LS, HS>(A, A.cur, A.items[4 * k], A.items[4 * k + 1], A.items[4 * k + 2]);
+}
+
+// batch form: items (i, j, set, l)
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_finish_batch(const BatchArgs B) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B.nitems) return;
+    finish_item<ST, LS, HS>(B.desc[B.items[4 * k + 3]], B.cur, B.items[4 * k], B.items[4 * k + 1],
+                            B.items[4 * k + 2]);
 }
 
 // One population t of the projection of a source node (set SS, absolute
@@ -920,27 +957,61 @@ __device__ void emit_pop(const Buf &b, int copy, int i, int j, double shift, int
 // one thread per (node, target population).  A.items lists (i, j) pairs:
 // the first A.nitems nodes of the low set project into the high set, the
 // next A.chunk nodes of the high set into the low set.
+// population t of the projection of node (i, j): up = low set into the
+// high set (with the learned closure cl6 if given), else high into low
 template <class ST, class LS, class HS>
-__global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n0 = (int64_t)A.nitems * HS::Q, n1 = (int64_t)A.chunk * LS::Q;
-    const int copy = A.cur ^ 1;
+__device__ __forceinline__ void project_entry(const StepArgs &A, const int cur, const bool up, const int i,
+                                              const int j, const int t, const float *cl6) {
+    const int copy = cur ^ 1;
     double rho, ux, uy;
-    if (k < n0) {
-        const int e = int(k / HS::Q), t = int(k % HS::Q);
-        const int i = A.items[2 * e], j = A.items[2 * e + 1];
+    if (up) {
         double fs[LS::Q];
         load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, fs);
-        const double v = project_one<LS, HS>(fs, t, rho, ux, uy, A.clo ? A.clo + 6 * e : nullptr);
+        const double v = project_one<LS, HS>(fs, t, rho, ux, uy, cl6);
         emit_pop<ST, HS>(A.other, copy, i, j, A.rho_shift, t, v, rho, ux, uy, A.g, A.ph);
-    } else if (k < n0 + n1) {
-        const int e = int((k - n0) / LS::Q) + A.nitems, t = int((k - n0) % LS::Q);
-        const int i = A.items[2 * e], j = A.items[2 * e + 1];
+    } else {
         double fs[HS::Q];
         load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, fs);
         const double v = project_one<HS, LS>(fs, t, rho, ux, uy);
         emit_pop<ST, LS>(A.self, copy, i, j, A.rho_shift, t, v, rho, ux, uy, A.g, A.ph);
     }
+}
+
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n0 = (int64_t)A.nitems * HS::Q, n1 = (int64_t)A.chunk * LS::Q;
+    if (k < n0) {
+        const int e = int(k / HS::Q), t = int(k % HS::Q);
+        project_entry<ST, LS, HS>(A, A.cur, true, A.items[2 * e], A.items[2 * e + 1], t,
+                                  A.clo ? A.clo + 6 * e : nullptr);
+    } else if (k < n0 + n1) {
+        const int e = int((k - n0) / LS::Q) + A.nitems, t = int((k - n0) % LS::Q);
+        project_entry<ST, LS, HS>(A, A.cur, false, A.items[2 * e], A.items[2 * e + 1], t, nullptr);
+    }
+}
+
+// batch form: items (i, j, l, 0); the first B.nitems entries project up,
+// the next B.nsplit down
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_project_halo_batch(const BatchArgs B) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n0 = (int64_t)B.nitems * HS::Q, n1 = (int64_t)B.nsplit * LS::Q;
+    int e, t;
+    bool up;
+    if (k < n0) {
+        e = int(k / HS::Q);
+        t = int(k % HS::Q);
+        up = true;
+    } else if (k < n0 + n1) {
+        e = int((k - n0) / LS::Q) + B.nitems;
+        t = int((k - n0) % LS::Q);
+        up = false;
+    } else {
+        return;
+    }
+    project_entry<ST, LS, HS>(B.desc[B.items[4 * e + 2]], B.cur, up, B.items[4 * e], B.items[4 * e + 1], t,
+                              nullptr);
 }
 
 // ------------------------------------------------------- learned closure

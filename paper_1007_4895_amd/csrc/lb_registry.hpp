@@ -15,6 +15,7 @@ using TimedFn = void (*)(const lbi::StepArgs &, int grid, hipStream_t, hipEvent_
 using NodeFn = void (*)(const lbi::NodeArgs &, int grid, hipStream_t);
 using IfaceFn = void (*)(const lbi::NodeArgs &, int copy, int recompute, int grid, hipStream_t);
 using ProjFn = void (*)(const double *, const double *, double *, int64_t, hipStream_t);
+using BatchFn = void (*)(const lbi::BatchArgs &, int grid, hipStream_t);
 
 struct KernelSet {
     int storage, nS, eqS, nO, eqO;
@@ -27,6 +28,9 @@ struct KernelSet {
     ProjFn project;        // FP64 projection self -> partner
     StepFn closure_infer;   // learned-closure inference of the lifted nodes (self = low set)
     NodeFn closure_samples; // training samples from an all-high run (self = high set)
+    BatchFn update_batch;   // batched forms (finish / projection: self = low set)
+    BatchFn finish_batch;
+    BatchFn project_batch;
     const void *update_kernel;   // the __global__ symbol (for attribute queries)
 };
 

@@ -291,6 +291,7 @@ struct lb_lattice {
     float *d_clo;               // closure coefficients of the lifted nodes
     ClosureNorm cn;
     int dom;                    // set whose update moves the most bytes per step
+    int64_t gen;                // bumped whenever the region map (work lists) changes
 };
 
 namespace {
@@ -315,14 +316,15 @@ int node_grid(const lb_lattice *L) { return (L->geo.nrow * L->geo.nx + 255) / 25
 // the group belongs to the set, cut into strips; the list is ordered
 // column-major so neighbouring strips are consecutive (and land on the same
 // XCD through the kernel's mapping)
-int build_items(const lb_lattice *L, int s, std::vector<int32_t> &out) {
-    out.clear();
+// maximal runs [j0, j1) of rows of set s per 60-column group (first column
+// in runcol); returns the total number of rows
+int set_runs(const lb_lattice *L, int s, std::vector<std::pair<int, int>> &runs, std::vector<int> &runcol) {
     const int nx = L->p.nx, ny = L->p.ny, nrow = ny + 1;
     const int want = s ? REG_HIGH : REG_LOW;
     const int ngrp = (nx + 59) / 60;
     int rows = 0;
-    std::vector<std::pair<int, int>> runs;
-    std::vector<int> runcol;
+    runs.clear();
+    runcol.clear();
     std::vector<char> inset(nrow);
     for (int w = 0; w < ngrp; ++w) {
         const int i0 = 60 * w, i1 = std::min(i0 + 60, nx);
@@ -346,13 +348,25 @@ int build_items(const lb_lattice *L, int s, std::vector<int32_t> &out) {
             j = j1;
         }
     }
+    return rows;
+}
+
+// rows per item when none is set: enough blocks to give every CU a few
+// resident ones
+int auto_strip(int64_t rows) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return int(std::max<int64_t>(1, std::min<int64_t>(16, rows / (8 * cus))));
+}
+
+int build_items(const lb_lattice *L, int s, std::vector<int32_t> &out) {
+    out.clear();
+    const int ngrp = (L->p.nx + 59) / 60;
+    std::vector<std::pair<int, int>> runs;
+    std::vector<int> runcol;
+    const int rows = set_runs(L, s, runs, runcol);
     int strip = L->strip[s];
-    if (strip <= 0) {
-        // enough blocks to give every CU a few resident ones
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        strip = std::max(1, std::min(16, rows / (8 * cus)));
-    }
+    if (strip <= 0) strip = auto_strip(rows);
     // Item order: the kernel gives XCD x the items [x * chunk, (x + 1) * chunk).
     // Each XCD gets a contiguous slab of column groups, and inside the slab
     // the strips are ordered row-major: blocks running together touch
@@ -481,6 +495,7 @@ lb_status upload_regions(lb_lattice *L) {
     if (L->nfin) HIPCHK(hipMemcpyAsync(L->d_fin, v.data(), v.size() * 4, hipMemcpyHostToDevice, L->stream));
     if (!pv.empty()) HIPCHK(hipMemcpyAsync(L->d_proj, pv.data(), pv.size() * 4, hipMemcpyHostToDevice, L->stream));
     HIPCHK(hipStreamSynchronize(L->stream));
+    L->gen++;
     return LB_OK;
 }
 
@@ -1142,6 +1157,376 @@ lb_status lb_kernel_times(lb_lattice *L, double *ms_high, int64_t *n_high, doubl
     if (n_all) *n_all = na;
     L->ev_used = 0;
     L->ev_kind.clear();
+    return LB_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+// Many independent lattices stepped together: per step, one launch per
+// kernel and velocity-set pair covers the work items of every lattice of
+// that pair (each item names its lattice, whose arguments sit in a device
+// descriptor table), optionally replayed from a captured HIP graph.
+
+struct lb_batch {
+    struct Kind {
+        const lbk::KernelSet *ks[2];   // the pair's kernels, self = low / high set
+        std::vector<int> members;      // lattice indices
+        int32_t *d_items[2] = {nullptr, nullptr};
+        int nitems[2] = {0, 0}, chunk[2] = {0, 0};
+        int32_t *d_fin = nullptr;
+        int nfin = 0;
+        int32_t *d_proj = nullptr;
+        int nup = 0, ndown = 0;
+    };
+    std::vector<lb_lattice *> lat;
+    std::vector<int64_t> gen;          // region generation of each lattice at the last build
+    std::vector<Kind> kinds;
+    hipStream_t stream;
+    StepArgs *d_desc[2];               // per lattice, self = low set / high set
+    int strip[2];                      // rows per work item (0 = automatic)
+    int cur;
+    int seg;                           // steps per captured graph (0 = direct launches)
+    hipGraph_t graph[2];               // one per starting copy parity
+    hipGraphExec_t exec[2];
+    hipEvent_t ev, t0, t1;
+    int64_t nodes;
+};
+
+namespace {
+
+lb_status upload_list(const std::vector<int32_t> &v, int32_t *&d, hipStream_t s) {
+    if (d) {
+        HIPCHK(hipFree(d));
+        d = nullptr;
+    }
+    if (v.empty()) return LB_OK;
+    HIPCHK(hipMalloc(&d, v.size() * 4));
+    HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+    return LB_OK;
+}
+
+void batch_drop_graphs(lb_batch *B) {
+    for (int p = 0; p < 2; ++p) {
+        if (B->exec[p]) (void)hipGraphExecDestroy(B->exec[p]);
+        if (B->graph[p]) (void)hipGraphDestroy(B->graph[p]);
+        B->exec[p] = nullptr;
+        B->graph[p] = nullptr;
+    }
+}
+
+// merged work lists of every pair kind
+lb_status batch_build(lb_batch *B) {
+    batch_drop_graphs(B);
+    std::vector<std::pair<int, int>> runs;
+    std::vector<int> runcol;
+    for (auto &K : B->kinds) {
+        for (int s = 0; s < 2; ++s) {
+            int64_t rows = 0;
+            for (int l : K.members) rows += set_runs(B->lat[l], s, runs, runcol);
+            const int strip = B->strip[s] > 0 ? B->strip[s] : auto_strip(rows);
+            // items ordered by lattice, column group and row, cut into 8
+            // contiguous slabs (one per XCD through the kernel's mapping) so
+            // neighbouring strips of one lattice share an L2
+            std::vector<int32_t> v;
+            for (int l : K.members) {
+                set_runs(B->lat[l], s, runs, runcol);
+                for (size_t r = 0; r < runs.size(); ++r)
+                    for (int j = runs[r].first; j < runs[r].second; j += strip) {
+                        v.push_back(runcol[r]);
+                        v.push_back(j);
+                        v.push_back(std::min(j + strip, runs[r].second));
+                        v.push_back(l);
+                    }
+            }
+            const int n = int(v.size() / 4);
+            K.chunk[s] = (n + 7) / 8;
+            v.resize(size_t(8) * K.chunk[s] * 4, 0);   // padding items are empty (j0 = j1)
+            K.nitems[s] = 8 * K.chunk[s];
+            lb_status st = upload_list(v, K.d_items[s], B->stream);
+            if (st != LB_OK) return st;
+        }
+        std::vector<int32_t> fin, up, down, f1, p1;
+        for (int l : K.members) {
+            lb_lattice *L = B->lat[l];
+            int np[2];
+            build_lists(L, f1, p1, np);
+            for (size_t k = 0; k < f1.size(); k += 4) {
+                fin.insert(fin.end(), {f1[k], f1[k + 1], f1[k + 2], l});
+            }
+            for (int e = 0; e < np[0] + np[1]; ++e) {
+                std::vector<int32_t> &d = e < np[0] ? up : down;
+                d.insert(d.end(), {p1[2 * e], p1[2 * e + 1], l, 0});
+            }
+        }
+        K.nfin = int(fin.size() / 4);
+        K.nup = int(up.size() / 4);
+        K.ndown = int(down.size() / 4);
+        up.insert(up.end(), down.begin(), down.end());
+        lb_status st = upload_list(fin, K.d_fin, B->stream);
+        if (st == LB_OK) st = upload_list(up, K.d_proj, B->stream);
+        if (st != LB_OK) return st;
+    }
+    HIPCHK(hipStreamSynchronize(B->stream));
+    for (size_t l = 0; l < B->lat.size(); ++l) B->gen[l] = B->lat[l]->gen;
+    return LB_OK;
+}
+
+// the launches of one step of every lattice (source copy cur)
+void batch_launch(lb_batch *B, int cur) {
+    for (auto &K : B->kinds)
+        for (int s = 0; s < 2; ++s) {
+            if (!K.chunk[s]) continue;
+            BatchArgs a{B->d_desc[s], K.d_items[s], K.nitems[s], K.chunk[s], cur, 0};
+            K.ks[s]->update_batch(a, 8 * K.chunk[s], B->stream);
+        }
+    for (auto &K : B->kinds) {
+        if (!(K.nup + K.ndown)) continue;
+        BatchArgs a{B->d_desc[0], K.d_proj, K.nup, 0, cur, K.ndown};
+        const int64_t nt = int64_t(K.nup) * K.ks[1]->nS * K.ks[1]->nS + int64_t(K.ndown) * K.ks[0]->nS * K.ks[0]->nS;
+        K.ks[0]->project_batch(a, int((nt + 127) / 128), B->stream);
+    }
+    for (auto &K : B->kinds) {
+        if (!K.nfin) continue;
+        BatchArgs a{B->d_desc[0], K.d_fin, K.nfin, 0, cur, 0};
+        K.ks[0]->finish_batch(a, (K.nfin + 127) / 128, B->stream);
+    }
+}
+
+lb_status batch_check(lb_batch *B) {
+    bool stale = false;
+    for (size_t l = 0; l < B->lat.size(); ++l) {
+        lb_lattice *L = B->lat[l];
+        if (L->cur != B->cur) return fail(LB_ESTATE, "lattice %zu was stepped outside the batch (copy parity)", l);
+        if (L->closure_on) return fail(LB_EUNSUPPORTED, "lattice %zu uses the learned closure", l);
+        if (L->gen != B->gen[l]) stale = true;
+    }
+    return stale ? batch_build(B) : LB_OK;
+}
+
+// order the batch stream after (into = true) or before the lattices' streams
+lb_status batch_join(lb_batch *B, bool into) {
+    std::vector<hipStream_t> seen;
+    for (lb_lattice *L : B->lat) {
+        if (L->stream == B->stream || std::find(seen.begin(), seen.end(), L->stream) != seen.end()) continue;
+        seen.push_back(L->stream);
+        if (into) {
+            HIPCHK(hipEventRecord(B->ev, L->stream));
+            HIPCHK(hipStreamWaitEvent(B->stream, B->ev, 0));
+        } else {
+            HIPCHK(hipEventRecord(B->ev, B->stream));
+            HIPCHK(hipStreamWaitEvent(L->stream, B->ev, 0));
+        }
+    }
+    return LB_OK;
+}
+
+lb_status batch_run(lb_batch *B, int64_t steps) {
+    int64_t k = 0;
+    if (B->seg > 0) {
+        while (steps - k >= B->seg) {
+            const int par = B->cur;
+            if (!B->exec[par]) {
+                HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+                for (int q = 0; q < B->seg; ++q) batch_launch(B, par ^ (q & 1));
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(B->stream, &g);
+                if (e != hipSuccess || !g) return fail(LB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+                B->graph[par] = g;
+                HIPCHK(hipGraphInstantiate(&B->exec[par], g, nullptr, nullptr, 0));
+            }
+            HIPCHK(hipGraphLaunch(B->exec[par], B->stream));
+            B->cur ^= B->seg & 1;
+            k += B->seg;
+        }
+    }
+    for (; k < steps; ++k) {
+        batch_launch(B, B->cur);
+        B->cur ^= 1;
+    }
+    HIPCHK(hipGetLastError());
+    for (lb_lattice *L : B->lat) {
+        L->cur = B->cur;
+        L->step += steps;
+    }
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stream, lb_batch **out) {
+    if (!lattices || n < 1 || !out) return fail(LB_EINVAL, "bad argument");
+    *out = nullptr;
+    const int cur = lattices[0] ? lattices[0]->cur : 0;
+    for (int l = 0; l < n; ++l) {
+        const lb_lattice *L = lattices[l];
+        if (!L) return fail(LB_EINVAL, "null lattice %d", l);
+        if (!L->initialized) return fail(LB_ESTATE, "lattice %d not initialised", l);
+        if (L->p.storage != lattices[0]->p.storage) return fail(LB_EINVAL, "lattices of one batch share a storage type");
+        if (L->p.iface != LB_IFACE_HERMITE) return fail(LB_EUNSUPPORTED, "batches use the Hermite interface");
+        if (L->closure_on) return fail(LB_EUNSUPPORTED, "lattice %d uses the learned closure", l);
+        if (L->cur != cur) return fail(LB_ESTATE, "lattices of one batch must be at the same copy parity");
+        for (int m = 0; m < l; ++m)
+            if (lattices[m] == L) return fail(LB_EINVAL, "lattice %d listed twice", l);
+    }
+    lb_batch *B = new lb_batch();
+    B->lat.assign(lattices, lattices + n);
+    B->gen.assign(n, -1);
+    B->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    B->strip[0] = B->strip[1] = 0;
+    B->cur = cur;
+    B->seg = 0;
+    B->graph[0] = B->graph[1] = nullptr;
+    B->exec[0] = B->exec[1] = nullptr;
+    B->d_desc[0] = B->d_desc[1] = nullptr;
+    B->ev = B->t0 = B->t1 = nullptr;
+    B->nodes = 0;
+    auto bail = [&](lb_status st) {
+        lb_batch_destroy(B);
+        return st;
+    };
+    std::vector<StepArgs> desc[2];
+    for (int l = 0; l < n; ++l) {
+        lb_lattice *L = B->lat[l];
+        B->nodes += int64_t(L->p.nx) * (L->p.ny + 1);
+        for (int s = 0; s < 2; ++s) {
+            StepArgs a{};
+            a.g = L->geo;
+            a.ph = L->ph;
+            a.rho_shift = L->rho_shift;
+            a.self = L->buf[s];
+            a.other = L->buf[1 - s];
+            a.ks = L->kconst[s];
+            a.self_high = s;
+            desc[s].push_back(a);
+        }
+        size_t k = 0;
+        while (k < B->kinds.size() && B->kinds[k].ks[0] != L->ks[0]) ++k;
+        if (k == B->kinds.size()) {
+            lb_batch::Kind K;
+            K.ks[0] = L->ks[0];
+            K.ks[1] = L->ks[1];
+            B->kinds.push_back(K);
+        }
+        B->kinds[k].members.push_back(l);
+    }
+    for (int s = 0; s < 2; ++s) {
+        if (hipMalloc(&B->d_desc[s], sizeof(StepArgs) * n) != hipSuccess) return bail(fail(LB_ENOMEM, "descriptor table"));
+        if (hipMemcpy(B->d_desc[s], desc[s].data(), sizeof(StepArgs) * n, hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(LB_EDEVICE, "descriptor upload failed"));
+    }
+    if (hipEventCreateWithFlags(&B->ev, hipEventDisableTiming) != hipSuccess || hipEventCreate(&B->t0) != hipSuccess ||
+        hipEventCreate(&B->t1) != hipSuccess)
+        return bail(fail(LB_EDEVICE, "event creation failed"));
+    lb_status st = batch_build(B);
+    if (st != LB_OK) return bail(st);
+    *out = B;
+    return LB_OK;
+}
+
+void lb_batch_destroy(lb_batch *B) {
+    if (!B) return;
+    if (B->stream) (void)hipStreamSynchronize(B->stream);
+    else (void)hipDeviceSynchronize();
+    batch_drop_graphs(B);
+    for (auto &K : B->kinds) {
+        for (int s = 0; s < 2; ++s)
+            if (K.d_items[s]) (void)hipFree(K.d_items[s]);
+        if (K.d_fin) (void)hipFree(K.d_fin);
+        if (K.d_proj) (void)hipFree(K.d_proj);
+    }
+    for (int s = 0; s < 2; ++s)
+        if (B->d_desc[s]) (void)hipFree(B->d_desc[s]);
+    if (B->ev) (void)hipEventDestroy(B->ev);
+    if (B->t0) (void)hipEventDestroy(B->t0);
+    if (B->t1) (void)hipEventDestroy(B->t1);
+    delete B;
+}
+
+lb_status lb_batch_set_graph(lb_batch *B, int32_t segment_steps) {
+    if (!B || segment_steps < 0) return fail(LB_EINVAL, "bad argument");
+    if (segment_steps > 0 && !B->stream) return fail(LB_EINVAL, "graph capture needs a created (non-null) stream");
+    if (segment_steps != B->seg) batch_drop_graphs(B);
+    B->seg = segment_steps;
+    return LB_OK;
+}
+
+lb_status lb_batch_set_strip_rows(lb_batch *B, int32_t rows_low, int32_t rows_high) {
+    if (!B || rows_low < 0 || rows_high < 0) return fail(LB_EINVAL, "bad argument");
+    B->strip[0] = rows_low;
+    B->strip[1] = rows_high;
+    return batch_build(B);
+}
+
+lb_status lb_batch_step(lb_batch *B, int64_t steps) {
+    if (!B || steps < 0) return fail(LB_EINVAL, "bad argument");
+    lb_status st = batch_check(B);
+    if (st == LB_OK) st = batch_join(B, true);
+    if (st == LB_OK) st = batch_run(B, steps);
+    if (st == LB_OK) st = batch_join(B, false);
+    return st;
+}
+
+lb_status lb_batch_autotune(lb_batch *B, int32_t steps, int32_t rows_out[2]) {
+    if (!B || steps < 1) return fail(LB_EINVAL, "bad argument");
+    lb_status st = batch_check(B);
+    if (st != LB_OK) return st;
+    // the trials advance the lattices: keep their states and restore them
+    std::vector<std::vector<char>> saved(B->lat.size());
+    for (size_t l = 0; l < B->lat.size(); ++l) {
+        saved[l].resize(lb_state_bytes(B->lat[l]));
+        if ((st = lb_get_state(B->lat[l], saved[l].data(), saved[l].size())) != LB_OK) return st;
+    }
+    const int cur0 = B->cur, seg0 = B->seg;
+    B->seg = 0;
+    static const int cand[] = {1, 2, 4, 8, 16, 32, 64};
+    if ((st = batch_join(B, true)) != LB_OK) return st;
+    for (int s = 0; s < 2; ++s) {
+        double best = 1e300;
+        int best_rows = 1;
+        for (int c : cand) {
+            B->strip[s] = c;
+            if ((st = batch_build(B)) != LB_OK) return st;
+            HIPCHK(hipEventRecord(B->t0, B->stream));
+            for (int k = 0; k < steps; ++k) {
+                batch_launch(B, B->cur);
+                B->cur ^= 1;
+            }
+            HIPCHK(hipEventRecord(B->t1, B->stream));
+            HIPCHK(hipEventSynchronize(B->t1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, B->t0, B->t1));
+            if (ms < best) {
+                best = ms;
+                best_rows = c;
+            }
+        }
+        B->strip[s] = best_rows;
+    }
+    if ((st = batch_build(B)) != LB_OK) return st;
+    B->cur = cur0;
+    B->seg = seg0;
+    for (size_t l = 0; l < B->lat.size(); ++l) {
+        lb_lattice *L = B->lat[l];
+        L->cur = cur0;
+        if ((st = lb_set_state(L, saved[l].data(), saved[l].size())) != LB_OK) return st;
+    }
+    if (rows_out) {
+        rows_out[0] = B->strip[0];
+        rows_out[1] = B->strip[1];
+    }
+    return LB_OK;
+}
+
+lb_status lb_batch_info(const lb_batch *B, int64_t *nodes, int32_t *launches_per_step, int32_t *kinds) {
+    if (!B) return fail(LB_EINVAL, "null batch");
+    int nl = 0;
+    for (auto &K : B->kinds) nl += (K.chunk[0] > 0) + (K.chunk[1] > 0) + (K.nup + K.ndown > 0) + (K.nfin > 0);
+    if (nodes) *nodes = B->nodes;
+    if (launches_per_step) *launches_per_step = nl;
+    if (kinds) *kinds = int32_t(B->kinds.size());
     return LB_OK;
 }
 

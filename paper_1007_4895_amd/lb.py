@@ -96,6 +96,13 @@ def lib():
                                           C.c_int64, _vp, _vp]),
             "lb_closure_samples": (C.c_int, [_vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp]),
             "lb_set_closure": (C.c_int, [_vp, _vp, C.POINTER(C.c_float)]),
+            "lb_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int32, _vp, C.POINTER(_vp)]),
+            "lb_batch_destroy": (None, [_vp]),
+            "lb_batch_set_graph": (C.c_int, [_vp, C.c_int32]),
+            "lb_batch_step": (C.c_int, [_vp, C.c_int64]),
+            "lb_batch_set_strip_rows": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+            "lb_batch_autotune": (C.c_int, [_vp, C.c_int32, _ip]),
+            "lb_batch_info": (C.c_int, [_vp, C.POINTER(C.c_int64), _ip, _ip]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -307,6 +314,54 @@ class Lattice:
         _check(lib().lb_closure_samples(self._h, _vp(nodes.data_ptr()), n, theta, _vp(x.data_ptr()),
                                         _vp(t.data_ptr()), _vp(f.data_ptr())))
         return x, t, f
+
+
+class Batch:
+    """Independent lattices stepped together (lb_batch_*): one launch per
+    kernel and velocity-set pair per step, optionally replayed from captured
+    HIP graphs.  Runs on its own created stream (graphs cannot capture the
+    null stream) and orders itself against the lattices' streams."""
+
+    def __init__(self, lattices, stream=None):
+        import torch
+
+        self.lattices = list(lattices)
+        n = len(self.lattices)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.lattices[0].device)
+        arr = (_vp * n)(*[L._h.value for L in self.lattices])
+        h = _vp()
+        _check(lib().lb_batch_create(arr, n, _vp(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, segment_steps):
+        _check(lib().lb_batch_set_graph(self._h, int(segment_steps)))
+
+    def step(self, n=1):
+        _check(lib().lb_batch_step(self._h, int(n)))
+
+    def set_strip_rows(self, low, high):
+        _check(lib().lb_batch_set_strip_rows(self._h, int(low), int(high)))
+
+    def autotune(self, steps=20):
+        out = (C.c_int32 * 2)()
+        _check(lib().lb_batch_autotune(self._h, int(steps), out))
+        return out[0], out[1]
+
+    def info(self):
+        nodes, nl, nk = C.c_int64(), C.c_int32(), C.c_int32()
+        _check(lib().lb_batch_info(self._h, C.byref(nodes), C.byref(nl), C.byref(nk)))
+        return nodes.value, nl.value, nk.value
 
 
 MLP_NIN, MLP_NH, MLP_NOUT, MLP_NREG = 10, 64, 8, 6

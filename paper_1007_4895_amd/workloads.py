@@ -16,6 +16,12 @@ Workloads (all synthetic: the paper's cases are analytic channel flows):
                = 2, outlet Kn = 0.2 (relaxation time ~ 1/rho), bands per
                64-column tile from the non-equilibrium indicator every 500
                steps, FP32 or BF16 storage.
+  batch_c5     128 independent channels, nx = 8 (periodic), ny uniform in
+               [32, 512], Kn log-spaced in [0.01, 1], near-wall bands of
+               8-64 rows (at most a third of the channel), velocity-set
+               pairs D2Q9/D2Q16, D2Q9/D2Q36 and D2Q16/D2Q36 in turn,
+               Couette and Poiseuille alternating, FP32, stepped as one
+               batch in graph-captured segments of 5000 steps.
 """
 from __future__ import annotations
 
@@ -67,3 +73,28 @@ POISEUILLE_C2 = dict(nx=1024, ny=512, kn=0.05, kn_sweep=(0.01, 0.05, 0.1), n_low
 PRESSURE_C3 = dict(nx=4096, ny=256, kn=0.2, n_low=D2Q9, n_high=D2Q36, eq_low=2, eq_high=4,
                    rho_in=2.0, rho_out=1.0, tile_w=64, theta=0.01, bmin=8, bmax=64, regrid=500,
                    cfl=0.3, storage="f32", steps=20000)
+
+BATCH_C5 = dict(count=128, nx=8, ny_range=(32, 512), kn_range=(0.01, 1.0), band_range=(8, 64),
+                pairs=((3, 2, 4, 3), (3, 2, 6, 4), (4, 3, 6, 4)), u_wall=0.05, gx=1e-6, storage="f32",
+                segment=5000, seed=51)
+
+
+def batch_cases(c=BATCH_C5, count=None):
+    """Seeded case list of the batch workload: per channel nx, ny, kn,
+    bands, velocity-set pair, wall velocities and body force."""
+    g = rng(c["seed"])
+    n = c["count"] if count is None else count
+    kns = np.geomspace(c["kn_range"][0], c["kn_range"][1], n)
+    nys = g.integers(c["ny_range"][0], c["ny_range"][1] + 1, n)
+    bands = g.integers(c["band_range"][0], c["band_range"][1] + 1, n)
+    out = []
+    for k in range(n):
+        ny = int(nys[k])
+        b = int(min(bands[k], ny // 3))
+        nl, el, nh, eh = c["pairs"][k % len(c["pairs"])]
+        couette = k % 2 == 0
+        out.append(dict(nx=c["nx"], ny=ny, kn=float(kns[k]), n_low=nl, eq_low=el, n_high=nh, eq_high=eh,
+                        bands=(b, b), storage=c["storage"],
+                        u_wall=((-c["u_wall"], 0.0), (c["u_wall"], 0.0)) if couette else ((0.0, 0.0), (0.0, 0.0)),
+                        gx=0.0 if couette else c["gx"]))
+    return out
