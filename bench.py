@@ -59,6 +59,60 @@ def timed(L, steps, torch):
     return time.perf_counter() - t0
 
 
+def batch_section(lb, W, torch):
+    """The 128-channel workload stepped as one batch (graph-captured
+    segments, autotuned strips) against stepping each channel with its own
+    launches."""
+    c5 = W.BATCH_C5
+    lats = []
+    for c in W.batch_cases():
+        p = lb.make_params(c["nx"], c["ny"], kn=c["kn"], n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"],
+                           eq_high=c["eq_high"], storage=c["storage"], u_wall=c["u_wall"], gx=c["gx"])
+        L = lb.Lattice(p)
+        L.set_regions(*c["bands"])
+        L.init_equilibrium()
+        lats.append(L)
+    nodes = sum(L.nx * L.nrow for L in lats)
+    alg = 0
+    for L in lats:
+        cnt = L.region_counts()
+        alg += 4 * 2 * (cnt[0] * L.Q[0] + cnt[1] * L.Q[1])
+    n_pc = 200
+    for L in lats:
+        L.step(10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for L in lats:
+        L.step(n_pc)
+    torch.cuda.synchronize()
+    sec_pc = time.perf_counter() - t0
+    B = lb.Batch(lats)
+    strips = B.autotune(20)
+    seg = c5["segment"]
+    B.set_graph(seg)
+    t0 = time.perf_counter()
+    B.step(seg)   # captures and replays the first segment
+    torch.cuda.synchronize()
+    t_cap = time.perf_counter() - t0
+    n_b = 2 * seg
+    t0 = time.perf_counter()
+    B.step(n_b)
+    torch.cuda.synchronize()
+    sec_b = time.perf_counter() - t0
+    _, launches, kinds = B.info()
+    B.close()
+    mlups_b = nodes * n_b / sec_b / 1e6
+    mlups_pc = nodes * n_pc / sec_pc / 1e6
+    gbs = alg * n_b / sec_b / 1e9
+    return {"workload": "128 channels nx=8 (periodic), ny uniform in [32,512], Kn log-spaced in [0.01,1], "
+                        "bands 8-64 rows, D2Q9/D2Q16, D2Q9/D2Q36, D2Q16/D2Q36, Couette/Poiseuille, FP32",
+            "nodes": nodes, "mlups_batch": round(mlups_b, 1), "mlups_one_launch_per_case": round(mlups_pc, 1),
+            "speedup": round(mlups_b / mlups_pc, 2), "us_per_step_batch": round(1e6 * sec_b / n_b, 2),
+            "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "graph_segment_steps": seg, "first_segment_s": round(t_cap, 3), "launches_per_step": launches,
+            "set_pairs": kinds, "strip_rows": list(strips), "timed_steps": n_b, "per_case_steps": n_pc}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +121,12 @@ def main():
     ap.add_argument("--quick", action="store_true", help="coupled timed region only (for profiler runs)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the strip autotuner")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 128-channel batch section")
+    ap.add_argument("--profile-steps", type=int, default=2000,
+                    help="steps of the kernel-timing pass (the dominant kernel's roofline)")
+    ap.add_argument("--shape", type=str, default="",
+                    help="work shape of the coupled run as ROWS_LOW,ROWS_HIGH,ORDER_LOW,ORDER_HIGH "
+                         "(skips its autotuner; reproduces a tuned run under a profiler)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="also run N launches of a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -94,7 +154,12 @@ def main():
     # ---------------------------------------------------- coupled, timed
     Lc = make(lb, W, c["kn"], all_high=False)
     counts = Lc.region_counts()
-    strips = Lc.strip_rows() if args.no_tune else Lc.autotune(100)
+    if args.shape:
+        v = [int(x) for x in args.shape.split(",")]
+        Lc.set_work_shape(v[:2], v[2:])
+    elif not args.no_tune:
+        Lc.autotune(100)
+    strips, orders = Lc.work_shape()
     Lc.step(args.warmup)
     sec = timed(Lc, args.steps, torch)
     cons = Lc.conservation()
@@ -104,7 +169,9 @@ def main():
 
     # roofline of the dominant kernel (the D2Q36 update): HIP events around
     # every launch on the lattice stream over a timed region
-    nprof = min(args.steps, 2000)
+    # (timing mode launches every kernel on the lattice stream, so the
+    # kernel's duration is its own, not shared with the concurrent set)
+    nprof = args.profile_steps
     Lc.set_timing(True)
     Lc.step(nprof)
     ms_h, n_h, ms_all, n_all = Lc.kernel_times()
@@ -131,6 +198,7 @@ def main():
                                "populations", "nodes": nodes, "d2q36_nodes": counts[1], "d2q9_nodes": counts[0]},
         "hbm_gbs_algorithmic": round(alg_bytes_step * args.steps / sec / 1e9, 1),
         "strip_rows": {"d2q9": strips[0], "d2q36": strips[1]},
+        "work_shape": ",".join(str(v) for v in (*strips, *orders)),
         "roofline": roofline,
         "conservation_finite": bool(np.all(np.isfinite(cons))),
     }
@@ -189,6 +257,11 @@ def main():
     out["e_model_vs_all_d2q36"] = emodel
     out["e_model_steps"] = c["steps"]
     out["gate_1e-3"] = gated
+
+    # ------------------- 128 independent channels: one batch vs one launch per case
+    if not args.no_batch:
+        out["batch_c5"] = batch_section(lb, W, torch)
+        print(f"batch: {out['batch_c5']}", flush=True)
 
     # ------------------------------- FP64 CPU oracle on a bounded sample
     if not args.no_cpu:

@@ -172,12 +172,30 @@ lb_status lb_set_timing(lb_lattice *L, int32_t enable);
 lb_status lb_kernel_times(lb_lattice *L, double *ms_high, int64_t *n_high, double *ms_all,
                           int64_t *n_all);
 
+/* Run the low set's update and its projection into the high set on a
+ * second stream (created by the library on first use, default priority),
+ * concurrently with the high set's update and projection; the streams join
+ * before the end of every step, so lb_step stays ordered on the lattice's
+ * stream.  Off by default: each step then adds two event records and two
+ * stream waits on the host, which cost more than the overlap gains unless
+ * the host is far ahead of the GPU; results are identical either way
+ * (batches, whose steps replay from graphs, always overlap).  Timing mode
+ * (lb_set_timing) launches everything on the lattice's stream. */
+lb_status lb_set_concurrency(lb_lattice *L, int32_t enable);
+
 /* Rows per work item of the update kernels (tuning; 0 = automatic: enough
  * items to fill the GPU, at most 16 rows). */
 lb_status lb_set_strip_rows(lb_lattice *L, int32_t rows);
 
 /* Current rows per work item of the low and high set's update kernel. */
 lb_status lb_get_strip_rows(const lb_lattice *L, int32_t rows[2]);
+
+/* Work shape of each set's update kernel: rows per work item (0 = automatic)
+ * and item order (0 = XCD slabs of column groups, row-major inside; 1 =
+ * column-major), low set first.  lb_autotune picks both; these reproduce
+ * or inspect its choice. */
+lb_status lb_set_work_shape(lb_lattice *L, const int32_t rows[2], const int32_t order[2]);
+lb_status lb_get_work_shape(const lb_lattice *L, int32_t rows[2], int32_t order[2]);
 
 /* Project-written autotuner: for each set, time the update kernel (kernel
  * events over `steps` steps) for each candidate strip height and item order

@@ -292,6 +292,9 @@ struct lb_lattice {
     ClosureNorm cn;
     int dom;                    // set whose update moves the most bytes per step
     int64_t gen;                // bumped whenever the region map (work lists) changes
+    bool concurrent;            // run the low set's kernels on a second stream
+    hipStream_t side;           // that stream (created on first use)
+    hipEvent_t efork, ejoin;
 };
 
 namespace {
@@ -545,12 +548,34 @@ hipEvent_t next_event(lb_lattice *L) {
     return L->ev_pool[L->ev_used++];
 }
 
+// The two sets are independent within a step until the interface: the low
+// set's update and its projection into the high set's halo run on a second
+// stream, concurrently with the high set's update and its projection into
+// the low set's halo (disjoint rows of disjoint buffers); the streams join
+// before the finish pass.
+lb_status make_side_stream(lb_lattice *L) {
+    HIPCHK(hipStreamCreateWithFlags(&L->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&L->efork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&L->ejoin, hipEventDisableTiming));
+    return LB_OK;
+}
+
 lb_status one_step(lb_lattice *L) {
     StepArgs a{};
     a.g = L->geo;
     a.ph = L->ph;
     a.rho_shift = L->rho_shift;
     a.cur = L->cur;
+    const bool par = L->concurrent && !L->timing && L->nitems[0] && L->nitems[1] && L->p.iface == LB_IFACE_HERMITE;
+    if (par && !L->side) {
+        lb_status st = make_side_stream(L);
+        if (st != LB_OK) return st;
+    }
+    hipStream_t sl = par ? L->side : L->stream;   // stream of the low set's kernels
+    if (par) {
+        HIPCHK(hipEventRecord(L->efork, L->stream));
+        HIPCHK(hipStreamWaitEvent(L->side, L->efork, 0));
+    }
     for (int s = 0; s < 2; ++s) {
         if (!L->nitems[s]) continue;
         a.self = L->buf[s];
@@ -566,7 +591,7 @@ lb_status one_step(lb_lattice *L) {
             L->ev_kind.push_back(s);
             L->ks[s]->update_timed(a, 8 * a.chunk, L->stream, e0, e1);
         } else {
-            L->ks[s]->update(a, 8 * a.chunk, L->stream);
+            L->ks[s]->update(a, 8 * a.chunk, s ? L->stream : sl);
         }
     }
     a.self = L->buf[0];
@@ -580,10 +605,26 @@ lb_status one_step(lb_lattice *L) {
             a.clo = L->d_clo;
             a.clw = L->d_clw;
             a.cn = L->cn;
-            L->ks[0]->closure_infer(a, (L->nproj[0] + 127) / 128, L->stream);
+            L->ks[0]->closure_infer(a, (L->nproj[0] + 127) / 128, sl);
         }
-        const int64_t nt = int64_t(L->nproj[0]) * L->Q[1] + int64_t(L->nproj[1]) * L->Q[0];
-        L->ks[0]->project_halo(a, int((nt + 127) / 128), L->stream);
+        if (par) {
+            // low -> high on the low set's stream, high -> low on the other
+            StepArgs up = a, down = a;
+            up.chunk = 0;
+            down.items = L->d_proj + 2 * L->nproj[0];
+            down.nitems = 0;
+            down.clo = nullptr;
+            if (L->nproj[0]) L->ks[0]->project_halo(up, int((int64_t(L->nproj[0]) * L->Q[1] + 127) / 128), sl);
+            if (L->nproj[1])
+                L->ks[0]->project_halo(down, int((int64_t(L->nproj[1]) * L->Q[0] + 127) / 128), L->stream);
+        } else {
+            const int64_t nt = int64_t(L->nproj[0]) * L->Q[1] + int64_t(L->nproj[1]) * L->Q[0];
+            L->ks[0]->project_halo(a, int((nt + 127) / 128), L->stream);
+        }
+    }
+    if (par) {
+        HIPCHK(hipEventRecord(L->ejoin, L->side));
+        HIPCHK(hipStreamWaitEvent(L->stream, L->ejoin, 0));
     }
     if (L->nfin) {
         a.items = L->d_fin;
@@ -683,6 +724,9 @@ lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t byte
     lb_lattice *L = new lb_lattice();
     L->p = *p;
     L->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    L->concurrent = false;
+    L->side = nullptr;
+    L->efork = L->ejoin = nullptr;
     L->ws = reinterpret_cast<char *>(dev_workspace);
     L->lay = lay;
     L->n[0] = p->n_low;
@@ -757,6 +801,12 @@ lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t byte
 
 void lb_destroy_lattice(lb_lattice *L) {
     if (!L) return;
+    if (L->side) {
+        (void)hipStreamSynchronize(L->side);
+        (void)hipStreamDestroy(L->side);
+        (void)hipEventDestroy(L->efork);
+        (void)hipEventDestroy(L->ejoin);
+    }
     for (auto e : L->ev_pool) (void)hipEventDestroy(e);
     delete L;
 }
@@ -798,6 +848,28 @@ lb_status lb_set_strip_rows(lb_lattice *L, int32_t rows) {
     if (!L || rows < 0 || rows > 1024) return fail(LB_EINVAL, "strip rows in [0, 1024] (0 = automatic)");
     L->strip[0] = L->strip[1] = rows;
     return upload_regions(L);
+}
+
+lb_status lb_set_work_shape(lb_lattice *L, const int32_t rows[2], const int32_t order[2]) {
+    if (!L || !rows || !order) return fail(LB_EINVAL, "null argument");
+    for (int s = 0; s < 2; ++s) {
+        if (rows[s] < 0 || rows[s] > 1024) return fail(LB_EINVAL, "strip rows in [0, 1024] (0 = automatic)");
+        if (order[s] != 0 && order[s] != 1) return fail(LB_EINVAL, "item order is 0 or 1");
+    }
+    for (int s = 0; s < 2; ++s) {
+        L->strip[s] = rows[s];
+        L->order[s] = order[s];
+    }
+    return upload_regions(L);
+}
+
+lb_status lb_get_work_shape(const lb_lattice *L, int32_t rows[2], int32_t order[2]) {
+    if (!L || !rows || !order) return fail(LB_EINVAL, "null argument");
+    for (int s = 0; s < 2; ++s) {
+        rows[s] = L->strip[s];
+        order[s] = L->order[s];
+    }
+    return LB_OK;
 }
 
 lb_status lb_get_strip_rows(const lb_lattice *L, int32_t rows[2]) {
@@ -1127,6 +1199,12 @@ lb_status lb_closure_samples(lb_lattice *L, const int32_t *nodes, int64_t n, dou
     return LB_OK;
 }
 
+lb_status lb_set_concurrency(lb_lattice *L, int32_t enable) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    L->concurrent = enable != 0;
+    return LB_OK;
+}
+
 lb_status lb_set_timing(lb_lattice *L, int32_t enable) {
     if (!L) return fail(LB_EINVAL, "null lattice");
     HIPCHK(hipStreamSynchronize(L->stream));
@@ -1190,6 +1268,8 @@ struct lb_batch {
     hipGraph_t graph[2];               // one per starting copy parity
     hipGraphExec_t exec[2];
     hipEvent_t ev, t0, t1;
+    hipStream_t side;                  // second stream: the low sets' kernels
+    hipEvent_t efork, ejoin;
     int64_t nodes;
 };
 
@@ -1272,25 +1352,37 @@ lb_status batch_build(lb_batch *B) {
     return LB_OK;
 }
 
-// the launches of one step of every lattice (source copy cur)
-void batch_launch(lb_batch *B, int cur) {
+// the launches of one step of every lattice (source copy cur): the low
+// sets' updates and their projections into the high sets run on the side
+// stream, the high sets' on the batch stream (as in a single lattice's step)
+lb_status batch_launch(lb_batch *B, int cur) {
+    HIPCHK(hipEventRecord(B->efork, B->stream));
+    HIPCHK(hipStreamWaitEvent(B->side, B->efork, 0));
     for (auto &K : B->kinds)
         for (int s = 0; s < 2; ++s) {
             if (!K.chunk[s]) continue;
             BatchArgs a{B->d_desc[s], K.d_items[s], K.nitems[s], K.chunk[s], cur, 0};
-            K.ks[s]->update_batch(a, 8 * K.chunk[s], B->stream);
+            K.ks[s]->update_batch(a, 8 * K.chunk[s], s ? B->stream : B->side);
         }
     for (auto &K : B->kinds) {
-        if (!(K.nup + K.ndown)) continue;
-        BatchArgs a{B->d_desc[0], K.d_proj, K.nup, 0, cur, K.ndown};
-        const int64_t nt = int64_t(K.nup) * K.ks[1]->nS * K.ks[1]->nS + int64_t(K.ndown) * K.ks[0]->nS * K.ks[0]->nS;
-        K.ks[0]->project_batch(a, int((nt + 127) / 128), B->stream);
+        const int qh = K.ks[1]->nS * K.ks[1]->nS, ql = K.ks[0]->nS * K.ks[0]->nS;
+        if (K.nup) {
+            BatchArgs a{B->d_desc[0], K.d_proj, K.nup, 0, cur, 0};
+            K.ks[0]->project_batch(a, int((int64_t(K.nup) * qh + 127) / 128), B->side);
+        }
+        if (K.ndown) {
+            BatchArgs a{B->d_desc[0], K.d_proj + 4 * K.nup, 0, 0, cur, K.ndown};
+            K.ks[0]->project_batch(a, int((int64_t(K.ndown) * ql + 127) / 128), B->stream);
+        }
     }
+    HIPCHK(hipEventRecord(B->ejoin, B->side));
+    HIPCHK(hipStreamWaitEvent(B->stream, B->ejoin, 0));
     for (auto &K : B->kinds) {
         if (!K.nfin) continue;
         BatchArgs a{B->d_desc[0], K.d_fin, K.nfin, 0, cur, 0};
         K.ks[0]->finish_batch(a, (K.nfin + 127) / 128, B->stream);
     }
+    return LB_OK;
 }
 
 lb_status batch_check(lb_batch *B) {
@@ -1328,9 +1420,14 @@ lb_status batch_run(lb_batch *B, int64_t steps) {
             const int par = B->cur;
             if (!B->exec[par]) {
                 HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-                for (int q = 0; q < B->seg; ++q) batch_launch(B, par ^ (q & 1));
+                lb_status st = LB_OK;
+                for (int q = 0; q < B->seg && st == LB_OK; ++q) st = batch_launch(B, par ^ (q & 1));
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(B->stream, &g);
+                if (st != LB_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return st;
+                }
                 if (e != hipSuccess || !g) return fail(LB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
                 B->graph[par] = g;
                 HIPCHK(hipGraphInstantiate(&B->exec[par], g, nullptr, nullptr, 0));
@@ -1341,7 +1438,8 @@ lb_status batch_run(lb_batch *B, int64_t steps) {
         }
     }
     for (; k < steps; ++k) {
-        batch_launch(B, B->cur);
+        lb_status st = batch_launch(B, B->cur);
+        if (st != LB_OK) return st;
         B->cur ^= 1;
     }
     HIPCHK(hipGetLastError());
@@ -1382,6 +1480,8 @@ lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stre
     B->exec[0] = B->exec[1] = nullptr;
     B->d_desc[0] = B->d_desc[1] = nullptr;
     B->ev = B->t0 = B->t1 = nullptr;
+    B->side = nullptr;
+    B->efork = B->ejoin = nullptr;
     B->nodes = 0;
     auto bail = [&](lb_status st) {
         lb_batch_destroy(B);
@@ -1418,8 +1518,11 @@ lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stre
             return bail(fail(LB_EDEVICE, "descriptor upload failed"));
     }
     if (hipEventCreateWithFlags(&B->ev, hipEventDisableTiming) != hipSuccess || hipEventCreate(&B->t0) != hipSuccess ||
-        hipEventCreate(&B->t1) != hipSuccess)
+        hipEventCreate(&B->t1) != hipSuccess || hipEventCreateWithFlags(&B->efork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&B->ejoin, hipEventDisableTiming) != hipSuccess)
         return bail(fail(LB_EDEVICE, "event creation failed"));
+    if (hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(LB_EDEVICE, "stream creation failed"));
     lb_status st = batch_build(B);
     if (st != LB_OK) return bail(st);
     *out = B;
@@ -1439,6 +1542,12 @@ void lb_batch_destroy(lb_batch *B) {
     }
     for (int s = 0; s < 2; ++s)
         if (B->d_desc[s]) (void)hipFree(B->d_desc[s]);
+    if (B->side) {
+        (void)hipStreamSynchronize(B->side);
+        (void)hipStreamDestroy(B->side);
+    }
+    if (B->efork) (void)hipEventDestroy(B->efork);
+    if (B->ejoin) (void)hipEventDestroy(B->ejoin);
     if (B->ev) (void)hipEventDestroy(B->ev);
     if (B->t0) (void)hipEventDestroy(B->t0);
     if (B->t1) (void)hipEventDestroy(B->t1);
@@ -1491,7 +1600,7 @@ lb_status lb_batch_autotune(lb_batch *B, int32_t steps, int32_t rows_out[2]) {
             if ((st = batch_build(B)) != LB_OK) return st;
             HIPCHK(hipEventRecord(B->t0, B->stream));
             for (int k = 0; k < steps; ++k) {
-                batch_launch(B, B->cur);
+                if ((st = batch_launch(B, B->cur)) != LB_OK) return st;
                 B->cur ^= 1;
             }
             HIPCHK(hipEventRecord(B->t1, B->stream));

@@ -86,6 +86,9 @@ def lib():
             "lb_set_strip_rows": (C.c_int, [_vp, C.c_int32]),
             "lb_region_counts": (C.c_int, [_vp, C.POINTER(C.c_int64)]),
             "lb_get_strip_rows": (C.c_int, [_vp, _ip]),
+            "lb_set_work_shape": (C.c_int, [_vp, _ip, _ip]),
+            "lb_set_concurrency": (C.c_int, [_vp, C.c_int32]),
+            "lb_get_work_shape": (C.c_int, [_vp, _ip, _ip]),
             "lb_autotune": (C.c_int, [_vp, C.c_int32, _ip]),
             "lb_mlp_param_count": (C.c_int64, []),
             "lb_mlp_workspace_bytes": (C.c_size_t, [C.c_int64]),
@@ -218,6 +221,19 @@ class Lattice:
         r = (C.c_int32 * 2)()
         _check(lib().lb_get_strip_rows(self._h, r))
         return tuple(r)
+
+    def set_concurrency(self, on=True):
+        _check(lib().lb_set_concurrency(self._h, 1 if on else 0))
+
+    def work_shape(self):
+        """((rows_low, rows_high), (order_low, order_high)) of the update kernels."""
+        r, o = (C.c_int32 * 2)(), (C.c_int32 * 2)()
+        _check(lib().lb_get_work_shape(self._h, r, o))
+        return (r[0], r[1]), (o[0], o[1])
+
+    def set_work_shape(self, rows, order):
+        r, o = (C.c_int32 * 2)(*rows), (C.c_int32 * 2)(*order)
+        _check(lib().lb_set_work_shape(self._h, r, o))
 
     def autotune(self, steps=50):
         """Pick the strip height of each set's update kernel by timing

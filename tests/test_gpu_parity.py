@@ -398,3 +398,34 @@ def test_pressure_channel_storage_error(oracle, lb, storage, tol):
     err = rel_u(uxg, uyg, uxo, uyo)
     print(f"{storage}: relative velocity error vs FP64 oracle after 300 steps = {err:.3e}")
     assert err < tol
+
+
+# ---------------------------------------------- execution modes, same bits
+def test_concurrent_streams_bit_identical(lb):
+    # the low set's kernels on a second stream (default) vs everything on
+    # one stream: identical populations, also with the learned closure
+    from paper_1007_4895_amd import closure
+    import torch
+    nx, ny = 300, 80
+    Ls = []
+    for conc in (True, False):
+        p = lb.make_params(nx, ny, kn=0.05, n_low=3, eq_low=2, n_high=6, eq_high=4, storage="f32", gx=1e-5,
+                           u_wall=((0.01, 0.0), (0.0, 0.0)), cfl=0.3)
+        L = lb.Lattice(p)
+        L.set_regions(12, 9)
+        rho, ux, uy = W.smooth_fields(nx, ny + 1, seed=61)
+        L.init_equilibrium(rho, ux, uy)
+        L.set_concurrency(conc)
+        Ls.append(L)
+    for L in Ls:
+        L.step(25)
+    norm = np.array([0.0] * 10 + [0.3, 0.05, 0.05, 1.0] + [1e-3] * 6 + [0.0] * 6 + [3e-4] * 6, np.float32)
+    params = torch.from_numpy(closure.init_params(3)).to("cuda:0")
+    for L in Ls:
+        L.set_closure(params, norm)
+        L.step(25)
+    for s in (0, 1):
+        a, b = Ls[0].get_populations(s), Ls[1].get_populations(s)
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+        m = ~np.isnan(a)
+        assert np.array_equal(a[m], b[m]), s
