@@ -76,6 +76,7 @@ struct StepArgs {
     int32_t nitems;      // work items (64 columns x a strip of rows)
     int32_t chunk;       // items per XCD slot (XCD-aware block mapping)
     const int32_t *items;   // device: 4 ints per item: i0, j0, j1, unused
+    uint32_t seed;          // per-step seed of stochastic rounding (bf16 storage)
     float *clo;             // per lifted node: the 6 closure coefficients (NULL = analytic)
     const uint16_t *clw;    // closure weights (bf16)
     ClosureNorm cn;
@@ -90,6 +91,7 @@ struct BatchArgs {
     int32_t chunk;          // update: items per XCD slot
     int32_t cur;            // source copy of every lattice
     int32_t nsplit;         // projection: entries projecting down
+    uint32_t seed;          // per-step seed of stochastic rounding (bf16 storage)
 };
 
 // Arguments of the non-step kernels (one thread per node).

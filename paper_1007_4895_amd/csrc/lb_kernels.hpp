@@ -50,6 +50,10 @@ struct StF64 {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v),
                                               r, vo, so, 0);
     }
+    static constexpr bool kSR = false;
+    __device__ static __forceinline__ void bst_r(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, M v, uint32_t) {
+        bst(r, vo, so, v);
+    }
 };
 
 struct StF32 {
@@ -65,6 +69,10 @@ struct StF32 {
     }
     __device__ static __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, M v) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+    }
+    static constexpr bool kSR = false;
+    __device__ static __forceinline__ void bst_r(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, M v, uint32_t) {
+        bst(r, vo, so, v);
     }
 };
 
@@ -89,7 +97,35 @@ struct StBF16 {
     __device__ static __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, M v) {
         __builtin_amdgcn_raw_buffer_store_b16(rne(v), r, vo, so, 0);
     }
+    // Stochastic rounding for the values the time step accumulates into:
+    // adding 16 uniform random bits below the kept ones and truncating
+    // rounds up with probability equal to the dropped fraction, so
+    // increments far below half an ulp still add up on average (with
+    // round-to-nearest they vanish and slow flows stall).
+    static constexpr bool kSR = true;
+    __device__ static __forceinline__ void bst_r(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so, M v,
+                                                 uint32_t rbits) {
+        const uint32_t u = __float_as_uint(v) + (rbits & 0xFFFFu);
+        __builtin_amdgcn_raw_buffer_store_b16(uint16_t(u >> 16), r, vo, so, 0);
+    }
 };
+
+// Counter-based 32-bit hash (the "lowbias32" xorshift-multiply mixer of
+// C. Wellons' hash-prospector search): the random bits of stochastic
+// rounding, a function of (step seed, node, population) only.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+template <class ST>
+__device__ __forceinline__ uint32_t sr_bits(uint32_t hnode, int a) {
+    if constexpr (ST::kSR) return mix32(hnode + uint32_t(a) * 0x85ebca77u);
+    else return 0u;
+}
 
 // ---------------------------------------------------------- lane exchange
 constexpr int DPP_WAVE_SHL1 = 0x130;   // lane l <- lane l+1
@@ -442,25 +478,25 @@ template <class SS>
 constexpr int update_waves() { return SS::Q == 36 ? 4 : SS::Q == 16 ? 4 : 6; }
 
 template <class ST, class SS, class OO, int WV>
-__device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const int i0, const int j0,
-                                            const int j1, const int lane);
+__device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
+                                            const int j0, const int j1, const int lane);
 
 // one work item (64 columns x rows j0..j1) of one lattice
 template <class ST, class SS, class OO>
-__device__ __forceinline__ void update_item(const StepArgs &A, const int cur, const int i0, const int j0,
-                                            const int j1) {
+__device__ __forceinline__ void update_item(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
+                                            const int j0, const int j1) {
     constexpr int SPLIT = update_split<SS>();
     const int lane = threadIdx.x & 63;
     // the wave index is wave-uniform: each wave runs the row loop compiled
     // for its own abscissae, so every population's upwind direction and
     // constants are known at compile time
     const int wv = SPLIT > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6) : 0;
-    if (wv == 0) update_rows<ST, SS, OO, 0>(A, cur, i0, j0, j1, lane);
+    if (wv == 0) update_rows<ST, SS, OO, 0>(A, cur, seed, i0, j0, j1, lane);
     if constexpr (SPLIT > 1) {
-        if (wv == 1) update_rows<ST, SS, OO, 1>(A, cur, i0, j0, j1, lane);
+        if (wv == 1) update_rows<ST, SS, OO, 1>(A, cur, seed, i0, j0, j1, lane);
     }
     if constexpr (SPLIT > 2) {
-        if (wv == 2) update_rows<ST, SS, OO, 2>(A, cur, i0, j0, j1, lane);
+        if (wv == 2) update_rows<ST, SS, OO, 2>(A, cur, seed, i0, j0, j1, lane);
     }
 }
 
@@ -475,7 +511,7 @@ void k_update(const StepArgs A) {
     if (it >= A.nitems) return;
     const int i0 = A.items[4 * it], j0 = A.items[4 * it + 1], j1 = A.items[4 * it + 2];
     if (j0 >= j1) return;   // padding item
-    update_item<ST, SS, OO>(A, A.cur, i0, j0, j1);
+    update_item<ST, SS, OO>(A, A.cur, A.seed, i0, j0, j1);
 }
 
 // The same update for a batch of independent lattices in one launch: item
@@ -491,12 +527,27 @@ void k_update_batch(const BatchArgs B) {
     const int i0 = B.items[4 * it], j0 = B.items[4 * it + 1], j1 = B.items[4 * it + 2];
     const int l = B.items[4 * it + 3];
     if (j0 >= j1) return;   // padding item
-    update_item<ST, SS, OO>(B.desc[l], B.cur, i0, j0, j1);
+    update_item<ST, SS, OO>(B.desc[l], B.cur, B.seed, i0, j0, j1);
 }
 
+// store of an updated value of population a in row j: stochastically
+// rounded where the storage type does that (bf16), plain otherwise.  The
+// random bits hash the step seed, the row and the population but not the
+// column: every copy of a value rounds alike, and a state uniform in x
+// stays uniform in x (the unsplit update is stable at Courant 0.5 only for
+// such states; column-dependent noise would seed growing 2D modes).
+#define LB_ST(voff, soff, val)                                                           \
+    {                                                                                    \
+        if constexpr (ST::kSR) {                                                         \
+            ST::bst_r(rd, voff, soff, val, sr_bits<ST>(uint32_t(j) * 0x9e3779b1u ^ seed, a)); \
+        } else {                                                                         \
+            ST::bst(rd, voff, soff, val);                                                \
+        }                                                                                \
+    }
+
 template <class ST, class SS, class OO, int WV>
-__device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const int i0, const int j0,
-                                            const int j1, const int lane) {
+__device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
+                                            const int j0, const int j1, const int lane) {
     using T = typename ST::M;
     using SV = typename ST::S;
     using TB = typename SS::T;
@@ -735,10 +786,10 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 // next row of this population (zero-cost past the strip end)
                 nw[k] = ST::bld(rs, vln, LB_SOFF(a, xq < 0.0 ? j + 3 : j + 2));
 
-                ST::bst(rd, vs, LB_SOFF(a, j), acc);
+                LB_ST(vs, LB_SOFF(a, j), acc)
                 if (wave_img) {
-                    ST::bst(rd, vimg_lo, LB_SOFF(a, j), acc);
-                    ST::bst(rd, vimg_hi, LB_SOFF(a, j), acc);
+                    LB_ST(vimg_lo, LB_SOFF(a, j), acc)
+                    LB_ST(vimg_hi, LB_SOFF(a, j), acc)
                 }
                 if (wall) {
                     // into the wall: bottom xi_y < 0, top xi_y > 0; those and
@@ -746,8 +797,8 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                     const bool leaving = bottom ? (xq > 0.0) : (xq < 0.0);
                     if (!leaving) {
                         if (xq != 0.0) nacc += T(lbt::cabs(xq)) * acc;
-                        ST::bst(rd, vs, LB_SOFF(a, gj1), acc);
-                        ST::bst(rd, vs, LB_SOFF(a, gj2), acc);
+                        LB_ST(vs, LB_SOFF(a, gj1), acc)
+                        LB_ST(vs, LB_SOFF(a, gj2), acc)
                     }
                 }
                 // keep the scheduler from hoisting every population's
@@ -783,12 +834,12 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 if constexpr (sizeof(T) == 8) sp = A.ks.sp[ws][a];
                 else sp = A.ks.spf[ws][a];
                 const T fl = d * T(TB::rule.w[a % N] * TB::rule.w[a / N]) + (d + rho_shift) * sp;
-                ST::bst(rd, vs, LB_SOFF(a, j), fl);
-                ST::bst(rd, vs, LB_SOFF(a, gj1), fl);
-                ST::bst(rd, vs, LB_SOFF(a, gj2), fl);
+                LB_ST(vs, LB_SOFF(a, j), fl)
+                LB_ST(vs, LB_SOFF(a, gj1), fl)
+                LB_ST(vs, LB_SOFF(a, gj2), fl)
                 if (wave_img) {
-                    ST::bst(rd, vimg_lo, LB_SOFF(a, j), fl);
-                    ST::bst(rd, vimg_hi, LB_SOFF(a, j), fl);
+                    LB_ST(vimg_lo, LB_SOFF(a, j), fl)
+                    LB_ST(vimg_hi, LB_SOFF(a, j), fl)
                 }
             }
         }
@@ -796,6 +847,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 #undef LB_SOFF
 #undef LB_POP
 }
+#undef LB_ST
 
 // Row images (periodic y) and pressure columns of the nodes listed in
 // A.items (i, j, set, 0): node-local, from the freshly written copy.

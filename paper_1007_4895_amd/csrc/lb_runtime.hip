@@ -548,6 +548,10 @@ hipEvent_t next_event(lb_lattice *L) {
     return L->ev_pool[L->ev_used++];
 }
 
+// seed of the stochastic rounding of step n (bf16 storage); the kernels hash
+// it with the row and the population
+uint32_t step_seed(int64_t n) { return uint32_t(uint64_t(n) * 0x9e3779b97f4a7c15ull >> 32); }
+
 // The two sets are independent within a step until the interface: the low
 // set's update and its projection into the high set's halo run on a second
 // stream, concurrently with the high set's update and its projection into
@@ -566,6 +570,7 @@ lb_status one_step(lb_lattice *L) {
     a.ph = L->ph;
     a.rho_shift = L->rho_shift;
     a.cur = L->cur;
+    a.seed = step_seed(L->step);
     const bool par = L->concurrent && !L->timing && L->nitems[0] && L->nitems[1] && L->p.iface == LB_IFACE_HERMITE;
     if (par && !L->side) {
         lb_status st = make_side_stream(L);
@@ -1355,23 +1360,23 @@ lb_status batch_build(lb_batch *B) {
 // the launches of one step of every lattice (source copy cur): the low
 // sets' updates and their projections into the high sets run on the side
 // stream, the high sets' on the batch stream (as in a single lattice's step)
-lb_status batch_launch(lb_batch *B, int cur) {
+lb_status batch_launch(lb_batch *B, int cur, uint32_t seed) {
     HIPCHK(hipEventRecord(B->efork, B->stream));
     HIPCHK(hipStreamWaitEvent(B->side, B->efork, 0));
     for (auto &K : B->kinds)
         for (int s = 0; s < 2; ++s) {
             if (!K.chunk[s]) continue;
-            BatchArgs a{B->d_desc[s], K.d_items[s], K.nitems[s], K.chunk[s], cur, 0};
+            BatchArgs a{B->d_desc[s], K.d_items[s], K.nitems[s], K.chunk[s], cur, 0, seed};
             K.ks[s]->update_batch(a, 8 * K.chunk[s], s ? B->stream : B->side);
         }
     for (auto &K : B->kinds) {
         const int qh = K.ks[1]->nS * K.ks[1]->nS, ql = K.ks[0]->nS * K.ks[0]->nS;
         if (K.nup) {
-            BatchArgs a{B->d_desc[0], K.d_proj, K.nup, 0, cur, 0};
+            BatchArgs a{B->d_desc[0], K.d_proj, K.nup, 0, cur, 0, seed};
             K.ks[0]->project_batch(a, int((int64_t(K.nup) * qh + 127) / 128), B->side);
         }
         if (K.ndown) {
-            BatchArgs a{B->d_desc[0], K.d_proj + 4 * K.nup, 0, 0, cur, K.ndown};
+            BatchArgs a{B->d_desc[0], K.d_proj + 4 * K.nup, 0, 0, cur, K.ndown, seed};
             K.ks[0]->project_batch(a, int((int64_t(K.ndown) * ql + 127) / 128), B->stream);
         }
     }
@@ -1379,7 +1384,7 @@ lb_status batch_launch(lb_batch *B, int cur) {
     HIPCHK(hipStreamWaitEvent(B->stream, B->ejoin, 0));
     for (auto &K : B->kinds) {
         if (!K.nfin) continue;
-        BatchArgs a{B->d_desc[0], K.d_fin, K.nfin, 0, cur, 0};
+        BatchArgs a{B->d_desc[0], K.d_fin, K.nfin, 0, cur, 0, seed};
         K.ks[0]->finish_batch(a, (K.nfin + 127) / 128, B->stream);
     }
     return LB_OK;
@@ -1421,7 +1426,9 @@ lb_status batch_run(lb_batch *B, int64_t steps) {
             if (!B->exec[par]) {
                 HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
                 lb_status st = LB_OK;
-                for (int q = 0; q < B->seg && st == LB_OK; ++q) st = batch_launch(B, par ^ (q & 1));
+                // (a replayed graph repeats its segment's seeds)
+                for (int q = 0; q < B->seg && st == LB_OK; ++q)
+                    st = batch_launch(B, par ^ (q & 1), step_seed(B->lat[0]->step + k + q));
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(B->stream, &g);
                 if (st != LB_OK) {
@@ -1438,7 +1445,7 @@ lb_status batch_run(lb_batch *B, int64_t steps) {
         }
     }
     for (; k < steps; ++k) {
-        lb_status st = batch_launch(B, B->cur);
+        lb_status st = batch_launch(B, B->cur, step_seed(B->lat[0]->step + k));
         if (st != LB_OK) return st;
         B->cur ^= 1;
     }
@@ -1600,7 +1607,7 @@ lb_status lb_batch_autotune(lb_batch *B, int32_t steps, int32_t rows_out[2]) {
             if ((st = batch_build(B)) != LB_OK) return st;
             HIPCHK(hipEventRecord(B->t0, B->stream));
             for (int k = 0; k < steps; ++k) {
-                if ((st = batch_launch(B, B->cur)) != LB_OK) return st;
+                if ((st = batch_launch(B, B->cur, step_seed(k))) != LB_OK) return st;
                 B->cur ^= 1;
             }
             HIPCHK(hipEventRecord(B->t1, B->stream));

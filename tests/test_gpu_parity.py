@@ -378,26 +378,61 @@ def test_pressure_channel_regrid_fp64(oracle, lb):
     assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
 
 
-@pytest.mark.parametrize("storage,tol", [
-    ("f32", 1e-5),
-    # bf16 with one constant shift w * rho_ref cannot follow this flow: the
-    # density spans 1..2, so stored values are ~w and their half-ulp
-    # (2^-9 w) exceeds the per-step increments, which round away (the flow
-    # stalls); measured error 0.74
-    pytest.param("bf16", 2e-3, marks=pytest.mark.xfail(strict=True, reason="bf16 round-to-nearest stalls: "
-                                                                                   "increments below half an ulp")),
-])
-def test_pressure_channel_storage_error(oracle, lb, storage, tol):
-    # reduced-precision population storage (weight-shifted) against the FP64
-    # oracle on the same pressure-driven channel (fixed bands)
+# Reduced-precision storage against FP64.  FP32 meets 1e-5 relative
+# velocity error.  bf16 (8-bit significand, stochastic rounding) carries
+# the velocity in population deviations of ~w |xi u|, so its error is set
+# by 2^-9 of those: the bounds below are its measured behaviour (stated
+# per result), and the 2e-3 goal is asserted separately as a known miss.
+BF16_GOAL = 2e-3
+
+
+def _c3_storage_error(oracle, lb, storage):
     G, O = _c3_small(oracle, lb, storage, 0)
     O.step(300)
     G.step(300)
     _, uxo, uyo = O.moments()
     _, uxg, uyg = G.moments()
-    err = rel_u(uxg, uyg, uxo, uyo)
+    return rel_u(uxg, uyg, uxo, uyo)
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("bf16", 5e-2)])
+def test_pressure_channel_storage_error(oracle, lb, storage, tol):
+    # pressure-driven channel (density 2 -> 1, Courant 0.3), fixed bands,
+    # reduced-precision storage against the FP64 oracle
+    err = _c3_storage_error(oracle, lb, storage)
     print(f"{storage}: relative velocity error vs FP64 oracle after 300 steps = {err:.3e}")
     assert err < tol
+
+
+def _c2_velocity(lb, storage, steps):
+    c = W.POISEUILLE_C2
+    p = lb.make_params(c["nx"], c["ny"], kn=c["kn"], n_low=3, eq_low=2, n_high=6, eq_high=4, gx=c["gx"],
+                       storage=storage)
+    L = lb.Lattice(p)
+    L.set_regions(*c["bands"])
+    L.init_equilibrium()
+    L.step(steps)
+    _, ux, uy = L.moments()
+    return ux, uy
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("bf16", 1e-2)])
+def test_poiseuille_c2_storage_error(lb, storage, tol):
+    # the full body-force channel (1024 x 513, 10k steps, Courant 0.5) in
+    # reduced precision against the same run with FP64 storage (which the
+    # coupled parity tests tie to the oracle at 1e-10)
+    c = W.POISEUILLE_C2
+    ref = _c2_velocity(lb, "f64", c["steps"])
+    u = _c2_velocity(lb, storage, c["steps"])
+    err = rel_u(u[0], u[1], ref[0], ref[1])
+    print(f"{storage}: relative velocity error vs FP64 after {c['steps']} steps = {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.xfail(strict=True, reason="bf16 storage misses the 2e-3 velocity-error goal (measured 5e-3 on the "
+                                       "body-force channel, 2e-2 on the pressure channel)")
+def test_bf16_storage_goal(oracle, lb):
+    assert _c3_storage_error(oracle, lb, "bf16") < BF16_GOAL
 
 
 # ---------------------------------------------- execution modes, same bits
