@@ -187,3 +187,79 @@ def lift_errors(params, norm, kn, f36, rho_ref=1.0, tau_rho=True, device="cuda:0
     torch.cuda.synchronize()
     a, l, t = fa.cpu().numpy(), fl.cpu().numpy(), src.cpu().numpy()
     return float(np.sqrt(np.sum((t - a) ** 2))), float(np.sqrt(np.sum((t - l) ** 2)))
+
+
+def velocity_error(L, ref):
+    """Relative L2 velocity error of lattice L against the field ref."""
+    _, ux, uy = L.moments()
+    return float(np.sqrt(np.sum((ux - ref[0]) ** 2 + (uy - ref[1]) ** 2) / np.sum(ref[0] ** 2 + ref[1] ** 2)))
+
+
+def report(nx=4096, ny=256, runs=8, steps=20000, snaps=16, per_snap=16384, train_steps=4000, kn_eval=0.2,
+           bands=(16, 16), seed=40):
+    """The learned closure on the pressure-driven channel: data from
+    all-D2Q36 runs (Kn log-uniform in [0.02, 0.5]), training on the GPU,
+    held-out sample and lift errors at kn_eval, and the coupled channel's
+    velocity error against all-D2Q36 with the analytic and the learned lift
+    (fixed bands).  Returns a dict."""
+    import time
+
+    import torch
+
+    out = {"geometry": f"{nx}x{ny + 1}", "runs": runs, "steps": steps}
+    kns = np.exp(W.rng(seed).uniform(np.log(0.02), np.log(0.5), runs))
+    t0 = time.perf_counter()
+    X, T, F, _ = generate(nx, ny, kns, steps=steps, snaps=snaps, per_snap=per_snap, seed=seed + 1)
+    out["samples"] = int(len(X))
+    out["data_s"] = round(time.perf_counter() - t0, 2)
+    out["kn_train"] = [round(float(k), 4) for k in kns]
+    norm = standardisation(X, T)
+    t0 = time.perf_counter()
+    params, hist = train(X, T, F, norm, steps=train_steps, batch=4096, lr=2e-3, seed=seed + 2, log_every=500)
+    out["train_s"] = round(time.perf_counter() - t0, 2)
+    out["loss"] = [(k, round(v, 5)) for k, v in hist]
+    e_tr, acc_tr = target_errors(params, X[:200000], T[:200000], F[:200000], norm)
+    del X, T, F
+    # held-out Kn: samples, lift errors, and the all-D2Q36 reference field
+    Xh, Th, Fh, _, Ph = generate(nx, ny, [kn_eval], steps=steps, snaps=4, per_snap=per_snap, seed=seed + 3,
+                                 keep_f36=True)
+    e_h, acc_h = target_errors(params, Xh, Th, Fh, norm)
+    la, ll = lift_errors(params, norm, kn_eval, Ph)
+    out["missing_coeff_rel_error"] = {"train": round(e_tr, 4), "held_out": round(e_h, 4), "analytic": 1.0}
+    out["flag_accuracy"] = {"train": round(acc_tr, 4), "held_out": round(acc_h, 4)}
+    out["lift_l2_error"] = {"analytic": la, "learned": ll, "ratio": round(ll / la, 4)}
+    A = channel(nx, ny, kn_eval, storage="f32")
+    A.step(steps)
+    _, ux, uy = A.moments()
+    ref = (ux, uy)
+    A.close()
+    flow = {}
+    for name, use in (("analytic", False), ("learned", True)):
+        L = channel(nx, ny, kn_eval, storage="f32", all_high=False, bands=bands)
+        if use:
+            L.set_closure(params, norm)
+        L.step(200)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.step(steps - 200)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        flow[name] = {"e_model": velocity_error(L, ref),
+                      "mlups": round(nx * (ny + 1) * (steps - 200) / sec / 1e6, 1)}
+        L.close()
+    out["coupled_vs_all_d2q36"] = {"kn_outlet": kn_eval, "bands": list(bands), **flow}
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="learned-closure report on the pressure-driven channel")
+    ap.add_argument("--small", action="store_true", help="reduced sizes (a quick check)")
+    a = ap.parse_args()
+    if a.small:
+        r = report(nx=512, ny=64, runs=4, steps=3000, snaps=4, per_snap=4096, train_steps=800, bands=(8, 8))
+    else:
+        r = report()
+    print(json.dumps(r))

@@ -23,7 +23,7 @@ struct Inst {
         hipLaunchKernelGGL((k_project_halo<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
     }
     static void closure_infer(const StepArgs &a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_closure_infer<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
+        hipLaunchKernelGGL((k_closure_infer<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
     }
     static void closure_samples(const NodeArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_closure_samples<ST, S, O>), dim3(grid), dim3(64), 0, s, a);

@@ -57,6 +57,9 @@ struct SetK {
     float spf[2][36], wKf[2], wDf[2];
 };
 
+// lifted nodes per wave of the closure inference kernel
+constexpr int CLOSURE_NB = 16;
+
 // Learned closure used by the lift (bf16 weights of the 10-64-64-8 network
 // and the standardisation constants) -- see lb_mlp.hip
 struct ClosureNorm {

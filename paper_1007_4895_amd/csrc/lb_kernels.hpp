@@ -1163,18 +1163,76 @@ __device__ void closure_coeffs(const W &w, const ClosureNorm &cn, const double *
 
 // Per step, before the projection pass: closure coefficients of the lifted
 // nodes (the first A.nitems entries of the projection list, low set).
+// One wave per CLOSURE_NB nodes, one lane per hidden unit: the lane keeps
+// its rows of the (bf16) weights in registers for all the wave's nodes,
+// and each layer's activations pass through LDS as broadcast reads.  The
+// features are computed by one lane per node first.
+
 template <class ST, class LS, class HS>
-__global__ __launch_bounds__(128) void k_closure_infer(const StepArgs A) {
+__global__ __launch_bounds__(64) void k_closure_infer(const StepArgs A) {
     if constexpr (LS::N == 3 && HS::N == 6) {
-        const int e = blockIdx.x * blockDim.x + threadIdx.x;
-        if (e >= A.nitems) return;
-        const int i = A.items[2 * e], j = A.items[2 * e + 1];
-        double f9[9];
-        load_node_d<ST, LS>(A.self, A.cur ^ 1, i, j, A.rho_shift, f9);
-        float c6[6];
-        closure_coeffs<LS>(WBf16{A.clw}, A.cn, f9, A.ph.rho_ref, c6);
+        __shared__ float xs[CLOSURE_NB][MLP_NIN];
+        __shared__ float rs[CLOSURE_NB];
+        __shared__ float h1s[MLP_NH], h2s[MLP_NH];
+        __shared__ float ps[MLP_NOUT][8];
+        const int lane = threadIdx.x;
+        const int e0 = blockIdx.x * CLOSURE_NB;
+        const int nn = min(CLOSURE_NB, A.nitems - e0);
+        if (lane < nn) {
+            const int e = e0 + lane;
+            const int i = A.items[2 * e], j = A.items[2 * e + 1];
+            double f9[9];
+            load_node_d<ST, LS>(A.self, A.cur ^ 1, i, j, A.rho_shift, f9);
+            double a00 = 0.0;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) A.clo[6 * e + k] = c6[k];
+            for (int al = 0; al < 9; ++al) a00 += f9[al];
+            // local Kn: Kn at rho_ref, scaled as 1/rho when the relaxation time is
+            const double kn_loc = A.cn.tau_rho ? A.cn.kn_ref * A.ph.rho_ref / a00 : A.cn.kn_ref;
+            double rho;
+            float x[MLP_NIN];
+            closure_features<LS>(f9, kn_loc, rho, x);
+#pragma unroll
+            for (int k = 0; k < MLP_NIN; ++k) xs[lane][k] = (x[k] - A.cn.xmean[k]) / A.cn.xstd[k];
+            rs[lane] = float(rho);
+        }
+        // this lane's weights: hidden unit `lane` of layers 1 and 2, and
+        // eight terms of output lane / 8 of layer 3
+        const uint16_t *w = A.clw;
+        float w1[MLP_NIN], w2[MLP_NH], w3[8];
+#pragma unroll
+        for (int k = 0; k < MLP_NIN; ++k) w1[k] = bf16_to_f(w[lane * MLP_NIN + k]);
+#pragma unroll
+        for (int k = 0; k < MLP_NH; ++k) w2[k] = bf16_to_f(w[MLP_OFF_W2 + lane * MLP_NH + k]);
+        const int oc = lane >> 3, part = lane & 7;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) w3[q] = bf16_to_f(w[MLP_OFF_W3 + oc * MLP_NH + part * 8 + q]);
+        const float b1 = bf16_to_f(w[MLP_OFF_B1 + lane]), b2 = bf16_to_f(w[MLP_OFF_B2 + lane]);
+        const float b3 = lane < MLP_NOUT ? bf16_to_f(w[MLP_OFF_B3 + lane]) : 0.0f;
+        __syncthreads();
+        for (int n = 0; n < nn; ++n) {
+            float s = b1;
+#pragma unroll
+            for (int k = 0; k < MLP_NIN; ++k) s += w1[k] * xs[n][k];
+            h1s[lane] = tanhf(s);
+            __syncthreads();
+            s = b2;
+#pragma unroll
+            for (int k = 0; k < MLP_NH; ++k) s += w2[k] * h1s[k];
+            h2s[lane] = tanhf(s);
+            __syncthreads();
+            float p = 0.0f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) p += w3[q] * h2s[part * 8 + q];
+            ps[oc][part] = p;
+            __syncthreads();
+            if (lane < 6) {
+                float y = b3;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) y += ps[lane][q];
+                A.clo[6 * (e0 + n) + lane] = rs[n] * (A.cn.tmean[lane] + A.cn.tstd[lane] * y);
+            }
+            __syncthreads();
+        }
     }
 }
 

@@ -610,7 +610,7 @@ lb_status one_step(lb_lattice *L) {
             a.clo = L->d_clo;
             a.clw = L->d_clw;
             a.cn = L->cn;
-            L->ks[0]->closure_infer(a, (L->nproj[0] + 127) / 128, sl);
+            L->ks[0]->closure_infer(a, (L->nproj[0] + lbi::CLOSURE_NB - 1) / lbi::CLOSURE_NB, sl);
         }
         if (par) {
             // low -> high on the low set's stream, high -> low on the other
