@@ -271,7 +271,7 @@ def main():
                            dt=0.5 / float(np.max(x)))
         O.set_regions(*c["bands"])
         O.init_equilibrium()
-        ns = 10
+        ns = 40
         t0 = time.perf_counter()
         O.step(ns)
         cs = time.perf_counter() - t0
