@@ -172,6 +172,13 @@ lb_status lb_set_timing(lb_lattice *L, int32_t enable);
 lb_status lb_kernel_times(lb_lattice *L, double *ms_high, int64_t *n_high, double *ms_all,
                           int64_t *n_all);
 
+/* Update both sets in one kernel launch (on by default; used when the low
+ * set is D2Q9 and both sets have nodes): the high set's work items and the
+ * D2Q9 items share the launch instead of running back to back.  Results
+ * are identical either way.  In timing mode the merged launch is the
+ * dominant kernel reported by lb_kernel_times. */
+lb_status lb_set_merged_update(lb_lattice *L, int32_t enable);
+
 /* Run the low set's update and its projection into the high set on a
  * second stream (created by the library on first use, default priority),
  * concurrently with the high set's update and projection; the streams join

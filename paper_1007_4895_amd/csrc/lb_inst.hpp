@@ -28,6 +28,15 @@ struct Inst {
     static void closure_samples(const NodeArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_closure_samples<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
     }
+    static void update_pair(const StepArgs &l, const StepArgs &h, int nb_h, int nb_l, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1) {
+        if (e0)
+            hipExtLaunchKernelGGL((k_update_pair<ST, S, O>), dim3(nb_h + nb_l), dim3(64 * update_split<O>()), 0, s, e0,
+                                  e1, 0, l, h, nb_h);
+        else
+            hipLaunchKernelGGL((k_update_pair<ST, S, O>), dim3(nb_h + nb_l), dim3(64 * update_split<O>()), 0, s, l, h,
+                               nb_h);
+    }
     static void update_batch(const BatchArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_update_batch<ST, S, O>), dim3(grid), dim3(64 * update_split<S>()), 0, s, a);
     }
@@ -87,6 +96,8 @@ struct Inst {
         k.project = &project;
         k.closure_infer = &closure_infer;
         k.closure_samples = &closure_samples;
+        k.update_pair = update_split<S>() == 1 ? &update_pair : nullptr;
+        k.pair_split = update_split<O>();
         k.update_batch = &update_batch;
         k.finish_batch = &finish_batch;
         k.project_batch = &project_batch;

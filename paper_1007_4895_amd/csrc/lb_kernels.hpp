@@ -514,6 +514,39 @@ void k_update(const StepArgs A) {
     update_item<ST, SS, OO>(A, A.cur, A.seed, i0, j0, j1);
 }
 
+// Both sets of a lattice in one launch, for a D2Q9 low set (one wave per
+// item): the first nb_h blocks run the high set's items (SPLIT waves per
+// item, as k_update), the rest give each of their SPLIT waves its own
+// D2Q9 item.  The two sets touch disjoint buffers, and one launch lets
+// their waves share the machine instead of running back to back.
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(64 * update_split<HS>())
+__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : update_waves<HS>())))
+void k_update_pair(const StepArgs L, const StepArgs H, const int nb_h) {
+    if constexpr (update_split<LS>() == 1) {
+        constexpr int SPLIT = update_split<HS>();
+        const int b = blockIdx.x;
+        if (b < nb_h) {
+            const int it = (b & 7) * H.chunk + (b >> 3);
+            if (it >= H.nitems) return;
+            const int i0 = H.items[4 * it], j0 = H.items[4 * it + 1], j1 = H.items[4 * it + 2];
+            if (j0 >= j1) return;
+            update_item<ST, HS, LS>(H, H.cur, H.seed, i0, j0, j1);
+        } else {
+            // low items: XCD slab (b' mod 8) of L.chunk items, SPLIT per block
+            const int bl = b - nb_h;
+            const int w = SPLIT > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6) : 0;
+            const int pos = SPLIT * (bl >> 3) + w;
+            if (pos >= L.chunk) return;
+            const int it = (bl & 7) * L.chunk + pos;
+            if (it >= L.nitems) return;
+            const int i0 = L.items[4 * it], j0 = L.items[4 * it + 1], j1 = L.items[4 * it + 2];
+            if (j0 >= j1) return;
+            update_rows<ST, LS, HS, 0>(L, L.cur, L.seed, i0, j0, j1, threadIdx.x & 63);
+        }
+    }
+}
+
 // The same update for a batch of independent lattices in one launch: item
 // (i0, j0, j1, l) belongs to lattice l, whose arguments are B.desc[l]; the
 // lattices of a batch step together, so the copy parity is the launch's.

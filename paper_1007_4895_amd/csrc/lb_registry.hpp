@@ -16,6 +16,10 @@ using NodeFn = void (*)(const lbi::NodeArgs &, int grid, hipStream_t);
 using IfaceFn = void (*)(const lbi::NodeArgs &, int copy, int recompute, int grid, hipStream_t);
 using ProjFn = void (*)(const double *, const double *, double *, int64_t, hipStream_t);
 using BatchFn = void (*)(const lbi::BatchArgs &, int grid, hipStream_t);
+// both sets' updates in one launch (self = low set, D2Q9 only): the blocks
+// of the high set come first
+using PairFn = void (*)(const lbi::StepArgs &low, const lbi::StepArgs &high, int nb_high, int nb_low, hipStream_t,
+                        hipEvent_t start, hipEvent_t stop);
 
 struct KernelSet {
     int storage, nS, eqS, nO, eqO;
@@ -28,6 +32,8 @@ struct KernelSet {
     ProjFn project;        // FP64 projection self -> partner
     StepFn closure_infer;   // learned-closure inference of the lifted nodes (self = low set)
     NodeFn closure_samples; // training samples from an all-high run (self = high set)
+    PairFn update_pair;     // NULL unless the low set is D2Q9
+    int pair_split;         // waves per block of update_pair (the high set's split)
     BatchFn update_batch;   // batched forms (finish / projection: self = low set)
     BatchFn finish_batch;
     BatchFn project_batch;

@@ -292,6 +292,8 @@ struct lb_lattice {
     ClosureNorm cn;
     int dom;                    // set whose update moves the most bytes per step
     int64_t gen;                // bumped whenever the region map (work lists) changes
+    bool merged;                // both sets' updates in one launch when the low set is D2Q9
+    bool tuning;                // inside the autotuner (per-set kernels)
     bool concurrent;            // run the low set's kernels on a second stream
     hipStream_t side;           // that stream (created on first use)
     hipEvent_t efork, ejoin;
@@ -581,7 +583,30 @@ lb_status one_step(lb_lattice *L) {
         HIPCHK(hipEventRecord(L->efork, L->stream));
         HIPCHK(hipStreamWaitEvent(L->side, L->efork, 0));
     }
-    for (int s = 0; s < 2; ++s) {
+    const bool merge = L->merged && !par && !L->tuning && L->nitems[0] && L->nitems[1] && L->ks[0]->update_pair;
+    if (merge) {
+        StepArgs sa[2] = {a, a};
+        for (int s = 0; s < 2; ++s) {
+            sa[s].self = L->buf[s];
+            sa[s].other = L->buf[1 - s];
+            sa[s].ks = L->kconst[s];
+            sa[s].self_high = s;
+            sa[s].items = L->d_items[s];
+            sa[s].nitems = L->nitems[s];
+            sa[s].chunk = (L->nitems[s] + 7) / 8;
+        }
+        const int sp = L->ks[0]->pair_split;
+        const int nb_h = 8 * sa[1].chunk, nb_l = 8 * ((sa[0].chunk + sp - 1) / sp);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (L->timing) {
+            e0 = next_event(L);
+            e1 = next_event(L);
+            if (!e0 || !e1) return fail(LB_EDEVICE, "event creation failed");
+            L->ev_kind.push_back(L->dom);   // the only update launch of the step
+        }
+        L->ks[0]->update_pair(sa[0], sa[1], nb_h, nb_l, L->stream, e0, e1);
+    }
+    for (int s = 0; s < 2 && !merge; ++s) {
         if (!L->nitems[s]) continue;
         a.self = L->buf[s];
         a.other = L->buf[1 - s];
@@ -730,6 +755,8 @@ lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t byte
     L->p = *p;
     L->stream = reinterpret_cast<hipStream_t>(hip_stream);
     L->concurrent = false;
+    L->merged = true;
+    L->tuning = false;
     L->side = nullptr;
     L->efork = L->ejoin = nullptr;
     L->ws = reinterpret_cast<char *>(dev_workspace);
@@ -892,6 +919,7 @@ lb_status lb_autotune(lb_lattice *L, int32_t steps, int32_t rows_out[2]) {
     lb_status st = lb_get_state(L, saved.data(), saved.size());
     if (st != LB_OK) return st;
     const int cur0 = L->cur;
+    L->tuning = true;   // time each set's kernel on its own
     static const int cand[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
     for (int s = 0; s < 2; ++s) {
         if (!L->count[s]) continue;
@@ -925,6 +953,7 @@ lb_status lb_autotune(lb_lattice *L, int32_t steps, int32_t rows_out[2]) {
         L->order[s] = best_order;
     }
     L->timing = false;
+    L->tuning = false;
     L->ev_used = 0;
     L->ev_kind.clear();
     if ((st = upload_regions(L)) != LB_OK) return st;
@@ -1201,6 +1230,12 @@ lb_status lb_closure_samples(lb_lattice *L, const int32_t *nodes, int64_t n, dou
     a.flag = flag;
     if (n) L->ks[1]->closure_samples(a, int((n + 63) / 64), L->stream);
     HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_set_merged_update(lb_lattice *L, int32_t enable) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    L->merged = enable != 0;
     return LB_OK;
 }
 

@@ -88,6 +88,7 @@ def lib():
             "lb_get_strip_rows": (C.c_int, [_vp, _ip]),
             "lb_set_work_shape": (C.c_int, [_vp, _ip, _ip]),
             "lb_set_concurrency": (C.c_int, [_vp, C.c_int32]),
+            "lb_set_merged_update": (C.c_int, [_vp, C.c_int32]),
             "lb_get_work_shape": (C.c_int, [_vp, _ip, _ip]),
             "lb_autotune": (C.c_int, [_vp, C.c_int32, _ip]),
             "lb_mlp_param_count": (C.c_int64, []),
@@ -221,6 +222,9 @@ class Lattice:
         r = (C.c_int32 * 2)()
         _check(lib().lb_get_strip_rows(self._h, r))
         return tuple(r)
+
+    def set_merged_update(self, on=True):
+        _check(lib().lb_set_merged_update(self._h, 1 if on else 0))
 
     def set_concurrency(self, on=True):
         _check(lib().lb_set_concurrency(self._h, 1 if on else 0))
