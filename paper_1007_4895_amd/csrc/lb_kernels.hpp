@@ -148,6 +148,20 @@ __device__ __forceinline__ double dpp(double src, double old) {
                                             ((unsigned long long)(unsigned)rhi << 32)));
 }
 
+// Neighbour-lane value for the update kernel's x fluxes: a lane without a
+// source lane (lane 0 for a right shift, 63 for a left shift) receives 0.
+// Only the halo lanes 0, 1, 62 and 63 ever see such a value, or one
+// derived from it, and their results are never stored; with no old value
+// to merge, the shift is one instruction.
+template <int CTRL>
+__device__ __forceinline__ float nbr(float src) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(src), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double nbr(double src) {
+    return dpp<CTRL>(src, src);
+}
+
 // minmod(a, b) = median(a, b, 0)
 __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 __device__ __forceinline__ double minmod(double a, double b) {
@@ -785,15 +799,15 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 
                 // x fluxes: neighbours from the adjacent lanes
                 if (xp != 0.0) {
-                    const T fm1 = dpp<DPP_WAVE_SHR1>(f, f);
-                    const T fp1 = dpp<DPP_WAVE_SHL1>(f, f);
+                    const T fm1 = nbr<DPP_WAVE_SHR1>(f);
+                    const T fp1 = nbr<DPP_WAVE_SHL1>(f);
                     const T dm = f - fm1, dp = fp1 - f;
                     if (xp > 0.0) {
-                        const T dmm = dpp<DPP_WAVE_SHR1>(dm, dm);
+                        const T dmm = nbr<DPP_WAVE_SHR1>(dm);
                         const T Lp = minmod(dm, dp), Lm = minmod(dmm, dm);
                         acc = acc - nu[p] * dm - kk[p] * (Lp - Lm);
                     } else {
-                        const T dpp_ = dpp<DPP_WAVE_SHL1>(dp, dp);
+                        const T dpp_ = nbr<DPP_WAVE_SHL1>(dp);
                         const T Lp = minmod(dpp_, dp), Lm = minmod(dp, dm);
                         acc = acc - nu[p] * dp - kk[p] * (Lp - Lm);
                     }
