@@ -491,26 +491,28 @@ __device__ __forceinline__ T (*lds_wall())[SPLIT][64] {
 template <class SS>
 constexpr int update_waves() { return SS::Q == 36 ? 4 : SS::Q == 16 ? 4 : 6; }
 
-template <class ST, class SS, class OO, int WV>
+template <class ST, class SS, class OO, int WV, bool NW = false>
 __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
-                                            const int j0, const int j1, const int lane);
+                                            const int j0, const int j1, const int lane, const int S = 0);
 
-// one work item (64 columns x rows j0..j1) of one lattice
-template <class ST, class SS, class OO>
+// one work item of one lattice: 64 columns x rows j0..j1, or (NW, a
+// narrow lattice) 64 / (nx + 4) lane groups of nx + 4 columns each, group
+// g marching rows j0 + g S .. j0 + (g + 1) S (clipped to j1)
+template <class ST, class SS, class OO, bool NW = false>
 __device__ __forceinline__ void update_item(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
-                                            const int j0, const int j1) {
+                                            const int j0, const int j1, const int S = 0) {
     constexpr int SPLIT = update_split<SS>();
     const int lane = threadIdx.x & 63;
     // the wave index is wave-uniform: each wave runs the row loop compiled
     // for its own abscissae, so every population's upwind direction and
     // constants are known at compile time
     const int wv = SPLIT > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6) : 0;
-    if (wv == 0) update_rows<ST, SS, OO, 0>(A, cur, seed, i0, j0, j1, lane);
+    if (wv == 0) update_rows<ST, SS, OO, 0, NW>(A, cur, seed, i0, j0, j1, lane, S);
     if constexpr (SPLIT > 1) {
-        if (wv == 1) update_rows<ST, SS, OO, 1>(A, cur, seed, i0, j0, j1, lane);
+        if (wv == 1) update_rows<ST, SS, OO, 1, NW>(A, cur, seed, i0, j0, j1, lane, S);
     }
     if constexpr (SPLIT > 2) {
-        if (wv == 2) update_rows<ST, SS, OO, 2>(A, cur, seed, i0, j0, j1, lane);
+        if (wv == 2) update_rows<ST, SS, OO, 2, NW>(A, cur, seed, i0, j0, j1, lane, S);
     }
 }
 
@@ -574,7 +576,10 @@ void k_update_batch(const BatchArgs B) {
     const int i0 = B.items[4 * it], j0 = B.items[4 * it + 1], j1 = B.items[4 * it + 2];
     const int l = B.items[4 * it + 3];
     if (j0 >= j1) return;   // padding item
-    update_item<ST, SS, OO>(B.desc[l], B.cur, B.seed, i0, j0, j1);
+    // a negative first column marks a narrow lattice's item: -i0 rows per
+    // lane group
+    if (i0 < 0) update_item<ST, SS, OO, true>(B.desc[l], B.cur, B.seed, 0, j0, j1, -i0);
+    else update_item<ST, SS, OO>(B.desc[l], B.cur, B.seed, i0, j0, j1);
 }
 
 // store of an updated value of population a in row j: stochastically
@@ -592,9 +597,9 @@ void k_update_batch(const BatchArgs B) {
         }                                                                                \
     }
 
-template <class ST, class SS, class OO, int WV>
+template <class ST, class SS, class OO, int WV, bool NW>
 __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
-                                            const int j0, const int j1, const int lane) {
+                                            const int j0, const int j1, const int lane, const int S) {
     using T = typename ST::M;
     using SV = typename ST::S;
     using TB = typename SS::T;
@@ -607,8 +612,20 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     static_assert(N % SPLIT == 0, "split must divide the abscissae");
     const Geo &g = A.g;
     const int nx = g.nx;
-    const int col = i0 - 2 + lane;
-    const bool valid = lane >= 2 && lane < 62 && col < nx;
+    // narrow lattices: lane group gl of nx + 4 lanes (2 halo columns each
+    // side) marches its own rows [jl0, jl1); wide: one group, rows [j0, j1)
+    int col, jl0 = j0, jl1 = j1;
+    bool valid;
+    if constexpr (NW) {
+        const int G = nx + 4, gl = lane / G;
+        col = lane - gl * G - 2;
+        jl0 = min(j0 + gl * S, j1);
+        jl1 = min(jl0 + S, j1);
+        valid = gl < 64 / G && col >= 0 && col < nx;
+    } else {
+        col = i0 - 2 + lane;
+        valid = lane >= 2 && lane < 62 && col < nx;
+    }
 
     // Addressing: raw buffer access with one descriptor per copy, the lane's
     // 32-bit byte offset (counted from column -2) in a vector register and
@@ -627,6 +644,10 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     const unsigned OOB = nbytes;
     const unsigned vl = unsigned(min(max(col, -2), nx + 1) + 2) * EB;
 #define LB_SOFF(a, j) unsigned(((int64_t)(a) * P + rb + (int64_t)((j) + 2) * pitch) * EB)
+    // narrow lattices: the row is per lane, so it moves into the vector
+    // offset and the scalar offset keeps the population only
+#define LB_VO(v, j) (NW ? (v) + unsigned((int64_t)((j) + 2) * pitch * EB) : (v))
+#define LB_SO(a, j) (NW ? unsigned(((int64_t)(a) * P + rb) * EB) : LB_SOFF(a, j))
 
     // region ownership of this lane's column (bands of its tile)
     const int tl = tile_of(min(max(col, 0), nx - 1), g);
@@ -653,7 +674,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 #pragma unroll
     for (int k = 0; k < QW; ++k) {
         const double xq = TB::rule.x[q0 + k / N];
-        nw[k] = ST::bld(rs, vl, LB_SOFF(LB_POP(k), xq < 0.0 ? j0 + 2 : j0 + 1));
+        nw[k] = ST::bld(rs, LB_VO(vl, xq < 0.0 ? jl0 + 2 : jl0 + 1), LB_SO(LB_POP(k), xq < 0.0 ? jl0 + 2 : jl0 + 1));
     }
     // y window per population: c = f_j; for xi_y > 0: s1 = f_j - f_{j-1},
     // s2 = minmod(f_{j-1} - f_{j-2}, f_j - f_{j-1}); for xi_y < 0:
@@ -664,21 +685,21 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
         const int a = LB_POP(k);
         const double xq = TB::rule.x[q0 + k / N];
         if (xq > 0.0) {
-            T fm2 = ST::bld(rs, vl, LB_SOFF(a, j0 - 2));
-            T fm1 = ST::bld(rs, vl, LB_SOFF(a, j0 - 1));
-            T f0 = ST::bld(rs, vl, LB_SOFF(a, j0));
+            T fm2 = ST::bld(rs, LB_VO(vl, jl0 - 2), LB_SO(a, jl0 - 2));
+            T fm1 = ST::bld(rs, LB_VO(vl, jl0 - 1), LB_SO(a, jl0 - 1));
+            T f0 = ST::bld(rs, LB_VO(vl, jl0), LB_SO(a, jl0));
             c[k] = f0;
             s1[k] = f0 - fm1;
             s2[k] = minmod(fm1 - fm2, f0 - fm1);
         } else if (xq < 0.0) {
-            T fm1 = ST::bld(rs, vl, LB_SOFF(a, j0 - 1));
-            T f0 = ST::bld(rs, vl, LB_SOFF(a, j0));
-            T fp1 = ST::bld(rs, vl, LB_SOFF(a, j0 + 1));
+            T fm1 = ST::bld(rs, LB_VO(vl, jl0 - 1), LB_SO(a, jl0 - 1));
+            T f0 = ST::bld(rs, LB_VO(vl, jl0), LB_SO(a, jl0));
+            T fp1 = ST::bld(rs, LB_VO(vl, jl0 + 1), LB_SO(a, jl0 + 1));
             c[k] = f0;
             s1[k] = fp1;
             s2[k] = minmod(fp1 - f0, f0 - fm1);
         } else {
-            c[k] = ST::bld(rs, vl, LB_SOFF(a, j0));
+            c[k] = ST::bld(rs, LB_VO(vl, jl0), LB_SO(a, jl0));
             s1[k] = T(0);
             s2[k] = T(0);
         }
@@ -688,7 +709,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     // images, pressure columns and partner-set projections are finished
     // afterwards by k_finish / k_project_halo
     const bool per_x = g.xbc == XBC_PERIODIC;
-    const bool wave_img = per_x && (i0 < 2 || i0 + 60 > nx - 2);   // uniform
+    const bool wave_img = per_x && (NW || i0 < 2 || i0 + 60 > nx - 2);   // uniform
 
     const T rho_shift = T(A.rho_shift);
     const T om0 = T(A.ph.omega0);
@@ -700,14 +721,21 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     T (*sm)[3][SPLIT][64] = lds_moments<T, SPLIT>();
     T (*sn)[SPLIT][64] = lds_wall<T, SPLIT>();
 
-    for (int j = j0; j < j1; ++j) {
-        const bool more = j + 1 < j1;
+    // (narrow: the loop counts a group's rows, S for every group)
+    for (int jr = NW ? 0 : j0; jr < (NW ? S : j1); ++jr) {
+        const int j = NW ? jl0 + jr : jr;
+        const bool more = jr + 1 < (NW ? S : j1);
         const unsigned vln = more ? vl : OOB;
-        const bool own = valid && reg_of(lo_l, hi_l, j, g) == want;
+        const bool own = valid && (!NW || j < jl1) && reg_of(lo_l, hi_l, j, g) == want;
         const unsigned vs = own ? unsigned(col + 2) * EB : OOB;
         const unsigned vimg_lo = (per_x && own && col < 2) ? unsigned(col + nx + 2) * EB : OOB;
         const unsigned vimg_hi = (per_x && own && col >= nx - 2) ? unsigned(col - nx + 2) * EB : OOB;
-        const bool wall = g.ybc == YBC_WALLS && (j == 0 || j == g.ny);
+        // wall rows: uniform for a wide item; per lane group for a narrow
+        // one, whose wall code runs when any lane has a wall row and only
+        // stores from those lanes
+        const bool wall_l = g.ybc == YBC_WALLS && (j == 0 || j == g.ny) && (!NW || j < jl1);
+        const bool wall = NW ? __builtin_amdgcn_ballot_w64(wall_l) != 0 : wall_l;
+        const unsigned vw = NW ? (wall_l ? vs : OOB) : vs;
         const bool bottom = j == 0;
         const int gj1 = bottom ? -1 : g.ny + 1, gj2 = bottom ? -2 : g.ny + 2;
         T nacc = T(0);
@@ -727,7 +755,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
             jy += T(TB::rule.x[q0 + qq]) * sq;
         }
         if constexpr (SPLIT > 1) {
-            const int buf = (j - j0) & 1;
+            const int buf = NW ? jr & 1 : (j - j0) & 1;
             sm[buf][0][wv][lane] = rp;
             sm[buf][1][wv][lane] = jx;
             sm[buf][2][wv][lane] = jy;
@@ -831,12 +859,12 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                     c[k] = nw[k];
                 }
                 // next row of this population (zero-cost past the strip end)
-                nw[k] = ST::bld(rs, vln, LB_SOFF(a, xq < 0.0 ? j + 3 : j + 2));
+                nw[k] = ST::bld(rs, LB_VO(vln, xq < 0.0 ? j + 3 : j + 2), LB_SO(a, xq < 0.0 ? j + 3 : j + 2));
 
-                LB_ST(vs, LB_SOFF(a, j), acc)
+                LB_ST(LB_VO(vs, j), LB_SO(a, j), acc)
                 if (wave_img) {
-                    LB_ST(vimg_lo, LB_SOFF(a, j), acc)
-                    LB_ST(vimg_hi, LB_SOFF(a, j), acc)
+                    LB_ST(LB_VO(vimg_lo, j), LB_SO(a, j), acc)
+                    LB_ST(LB_VO(vimg_hi, j), LB_SO(a, j), acc)
                 }
                 if (wall) {
                     // into the wall: bottom xi_y < 0, top xi_y > 0; those and
@@ -844,8 +872,8 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                     const bool leaving = bottom ? (xq > 0.0) : (xq < 0.0);
                     if (!leaving) {
                         if (xq != 0.0) nacc += T(lbt::cabs(xq)) * acc;
-                        LB_ST(vs, LB_SOFF(a, gj1), acc)
-                        LB_ST(vs, LB_SOFF(a, gj2), acc)
+                        LB_ST(LB_VO(vw, gj1), LB_SO(a, gj1), acc)
+                        LB_ST(LB_VO(vw, gj2), LB_SO(a, gj2), acc)
                     }
                 }
                 // keep the scheduler from hoisting every population's
@@ -881,17 +909,21 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 if constexpr (sizeof(T) == 8) sp = A.ks.sp[ws][a];
                 else sp = A.ks.spf[ws][a];
                 const T fl = d * T(TB::rule.w[a % N] * TB::rule.w[a / N]) + (d + rho_shift) * sp;
-                LB_ST(vs, LB_SOFF(a, j), fl)
-                LB_ST(vs, LB_SOFF(a, gj1), fl)
-                LB_ST(vs, LB_SOFF(a, gj2), fl)
+                const unsigned vil = NW ? (wall_l ? vimg_lo : OOB) : vimg_lo;
+                const unsigned vih = NW ? (wall_l ? vimg_hi : OOB) : vimg_hi;
+                LB_ST(LB_VO(vw, j), LB_SO(a, j), fl)
+                LB_ST(LB_VO(vw, gj1), LB_SO(a, gj1), fl)
+                LB_ST(LB_VO(vw, gj2), LB_SO(a, gj2), fl)
                 if (wave_img) {
-                    LB_ST(vimg_lo, LB_SOFF(a, j), fl)
-                    LB_ST(vimg_hi, LB_SOFF(a, j), fl)
+                    LB_ST(LB_VO(vil, j), LB_SO(a, j), fl)
+                    LB_ST(LB_VO(vih, j), LB_SO(a, j), fl)
                 }
             }
         }
     }
 #undef LB_SOFF
+#undef LB_VO
+#undef LB_SO
 #undef LB_POP
 }
 #undef LB_ST

@@ -1351,11 +1351,16 @@ lb_status batch_build(lb_batch *B) {
             std::vector<int32_t> v;
             for (int l : K.members) {
                 set_runs(B->lat[l], s, runs, runcol);
+                // a lattice at most 28 columns wide packs 64 / (nx + 4) lane
+                // groups into a wave, each marching `strip` rows of its own;
+                // such items carry -strip as their first column
+                const int ng = 64 / (B->lat[l]->p.nx + 4);
+                const int span = ng >= 2 ? ng * strip : strip;
                 for (size_t r = 0; r < runs.size(); ++r)
-                    for (int j = runs[r].first; j < runs[r].second; j += strip) {
-                        v.push_back(runcol[r]);
+                    for (int j = runs[r].first; j < runs[r].second; j += span) {
+                        v.push_back(ng >= 2 ? -strip : runcol[r]);
                         v.push_back(j);
-                        v.push_back(std::min(j + strip, runs[r].second));
+                        v.push_back(std::min(j + span, runs[r].second));
                         v.push_back(l);
                     }
             }
