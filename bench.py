@@ -124,6 +124,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the strip autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the 128-channel batch section")
+    ap.add_argument("--batch-only", action="store_true", help="run only the 128-channel batch section (profiling)")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="steps of the kernel-timing pass (the dominant kernel's roofline)")
     ap.add_argument("--shape", type=str, default="",
@@ -144,6 +145,9 @@ def main():
     c = W.POISEUILLE_C2
     nodes = c["nx"] * (c["ny"] + 1)
     torch.cuda.init()
+    if args.batch_only:
+        print(json.dumps({"batch_c5": batch_section(lb, W, torch)}))
+        return
 
     if args.copy_calib:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
