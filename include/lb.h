@@ -260,8 +260,9 @@ lb_status lb_closure_samples(lb_lattice *L, const int32_t *nodes, int64_t n, dou
                              int32_t *flag);
 
 /* Use the network in every D2Q9 -> D2Q36 lift of this lattice (params
- * device FP32, norm host [32]); params == NULL restores the analytic
- * projection.  Waits. */
+ * device FP32, norm host [32]): the halo lift at the end of every step,
+ * nodes switched to D2Q36 by a region change, and the halo rebuilt after
+ * it.  params == NULL restores the analytic projection.  Waits. */
 lb_status lb_set_closure(lb_lattice *L, const float *params, const float *norm);
 
 /* ---------------------------------------------------------------------

@@ -116,6 +116,8 @@ struct NodeArgs {
     double theta;
     float *fx, *ft;                  // sample features / targets
     int32_t *flag;
+    const uint16_t *clw;             // learned closure weights (bf16) for region-change lifts, or NULL
+    ClosureNorm cn;
 };
 
 }  // namespace lbi

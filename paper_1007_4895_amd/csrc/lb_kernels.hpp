@@ -1513,6 +1513,24 @@ __global__ void k_convert(const NodeArgs A) {
         load_node_d<ST, OO>(A.other, A.cur, i, j, A.rho_shift, fo);
         const double *cl = nullptr;
         if (A.closure && A.self_high) cl = A.closure + (int64_t)(j * A.g.nx + i) * SS::Q;
+        double cl36[SS::Q];
+        if constexpr (OO::N == 3 && SS::N == 6) {
+            // D2Q9 -> D2Q36 with the learned closure: the network's six
+            // coefficients, zero elsewhere
+            if (A.clw && A.self_high) {
+                float c6[6];
+                closure_coeffs<OO>(WBf16{A.clw}, A.cn, fo, A.ph.rho_ref, c6);
+#pragma unroll
+                for (int q = 0; q < SS::Q; ++q) cl36[q] = 0.0;
+                cl36[3 * 6 + 0] = c6[0];
+                cl36[0 * 6 + 3] = c6[1];
+                cl36[3 * 6 + 1] = c6[2];
+                cl36[1 * 6 + 3] = c6[3];
+                cl36[4 * 6 + 0] = c6[4];
+                cl36[0 * 6 + 4] = c6[5];
+                cl = cl36;
+            }
+        }
         project_d<OO, SS>(fo, fs, cl);
         store_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, fs);
     }

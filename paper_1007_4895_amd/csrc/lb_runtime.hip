@@ -1156,10 +1156,34 @@ lb_status lb_change_regions(lb_lattice *L, const int32_t *lo, const int32_t *hi)
         NodeArgs a = node_args(L, s, L->cur);
         a.oblo = L->d_oblo;
         a.obhi = L->d_obhi;
+        if (L->closure_on) {
+            a.clw = L->d_clw;
+            a.cn = L->cn;
+        }
         L->ks[s]->convert(a, node_grid(L), L->stream);
     }
     st = refresh_all(L, 1);
     if (st != LB_OK) return st;
+    if (L->closure_on && L->nproj[0]) {
+        // the halo lift of the current copy with the learned closure, as
+        // every step does for its new copy
+        StepArgs a{};
+        a.g = L->geo;
+        a.ph = L->ph;
+        a.rho_shift = L->rho_shift;
+        a.cur = L->cur ^ 1;   // the kernels act on copy cur ^ 1
+        a.self = L->buf[0];
+        a.other = L->buf[1];
+        a.items = L->d_proj;
+        a.nitems = L->nproj[0];
+        a.chunk = 0;
+        a.clo = L->d_clo;
+        a.clw = L->d_clw;
+        a.cn = L->cn;
+        L->ks[0]->closure_infer(a, (L->nproj[0] + lbi::CLOSURE_NB - 1) / lbi::CLOSURE_NB, L->stream);
+        L->ks[0]->project_halo(a, int((int64_t(L->nproj[0]) * L->Q[1] + 127) / 128), L->stream);
+        HIPCHK(hipGetLastError());
+    }
     HIPCHK(hipStreamSynchronize(L->stream));
     return LB_OK;
 }

@@ -220,6 +220,42 @@ def test_step_with_learned_closure(oracle, lb, mlp):
     assert d > 1e-7, d
 
 
+def test_region_change_with_learned_closure(oracle, lb, mlp):
+    # nodes switched from D2Q9 to D2Q36 by a region change, and the halo
+    # rebuilt after it, are lifted with the network; the oracle converts
+    # with the same closure computed from its own D2Q9 state
+    nx, ny, kn = 130, 40, 0.2
+    G, O = _pressure_pair(oracle, lb, nx, ny, kn, "f64", (6, 8))
+    G.step(40)
+    O.step(40)
+    p, _, _, _ = _net(mlp, 13, 1)
+    norm = _trial_norm()
+    G.set_closure(_dev(p), norm)
+    f9 = O.get_populations(0)
+    reg = O.region()
+    c = np.zeros((36, ny + 1, nx))
+    for j in range(ny + 1):
+        for i in range(nx):
+            if reg[j, i] == oracle.REG_LOW:
+                c[:, j, i] = _oracle_closure(oracle, mlp, p, norm, kn, f9[:, j, i])
+    O.set_closure(c)
+    lo, hi = np.full(G.ntiles, 11, np.int32), np.full(G.ntiles, 12, np.int32)
+    G.change_regions(lo, hi)
+    O.update_regions(lo, hi)
+    for s in (0, 1):
+        gpop, opop = G.get_populations(s), O.get_populations(s)
+        m = ~np.isnan(gpop[0])
+        e = np.max(np.abs(gpop[:, m] - opop[:, m])) / np.max(np.abs(opop[:, m]))
+        assert e < 1e-9, ("after the change", s, e)
+    G.step(1)
+    O.step(1)
+    for s in (0, 1):
+        gpop, opop = G.get_populations(s), O.get_populations(s)
+        m = ~np.isnan(gpop[0])
+        e = np.max(np.abs(gpop[:, m] - opop[:, m])) / np.max(np.abs(opop[:, m]))
+        assert e < 1e-9, ("one step later", s, e)
+
+
 def test_closure_training_gain(oracle, lb):
     # train on all-D2Q36 pressure-channel runs (Kn log-uniform in
     # [0.02, 0.5]) with the library's kernels; on a held-out Kn the learned
