@@ -247,7 +247,9 @@ lb_status lb_mlp_adam(float *params, const float *grad, float *m, float *v, int6
 
 /* Closure coefficients (row-major 6x6 Hermite indices, zero outside the six
  * predicted components) of n D2Q9 nodes given as FP64 absolute populations
- * [n][9]; norm is a host array of 32 floats; bf16 weights.  Test hook. */
+ * [n][9]; norm is a host array of 32 floats.  Evaluated as in the lift:
+ * bf16 weights on the matrix cores.  Test hook: allocates a temporary copy
+ * of the weights (stream-ordered). */
 lb_status lb_closure_eval(const float *params, const float *norm, double kn_ref, int32_t tau_rho, double rho_ref,
                           const double *f9, int64_t n, double *c36, void *hip_stream);
 

@@ -1240,78 +1240,153 @@ __device__ void closure_coeffs(const W &w, const ClosureNorm &cn, const double *
     for (int k = 0; k < 6; ++k) c6[k] = float(rho) * (cn.tmean[k] + cn.tstd[k] * y[k]);
 }
 
-// Per step, before the projection pass: closure coefficients of the lifted
-// nodes (the first A.nitems entries of the projection list, low set).
-// One wave per CLOSURE_NB nodes, one lane per hidden unit: the lane keeps
-// its rows of the (bf16) weights in registers for all the wave's nodes,
-// and each layer's activations pass through LDS as broadcast reads.  The
-// features are computed by one lane per node first.
+// The network on the matrix cores: one wave evaluates 16 nodes with
+// v_mfma_f32_16x16x16_bf16 tiles (nodes x hidden units), weights as their
+// bf16 bits, FP32 accumulation.  Inputs and activations enter as two bf16
+// terms (hi + lo, 16 significant bits together), so the result carries the
+// FP32 network's accuracy rather than bf16 activations'.  Operand layouts
+// (16 x 16 x 16): A[i][k] in lane i + 16 (k / 4), element k % 4; B[k][j] in
+// lane j + 16 (k / 4), element k % 4; D[i][j] in lane j + 16 (i / 4),
+// register i % 4.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
+__device__ __forceinline__ void bf16_split(float v, short &hi, short &lo) {
+    const uint16_t h = f_to_bf16(v);
+    hi = short(h);
+    lo = short(f_to_bf16(v - bf16_to_f(h)));
+}
+
+// xs: standardised inputs of the 16 nodes (K padded to 16 with zeros);
+// hs: LDS scratch [16][64 + 4]; out: c6 of the 16 nodes (rho * (mean + std y))
+__device__ __forceinline__ void closure_mfma16(const uint16_t *w, const ClosureNorm &cn, const float (*xs)[16],
+                                               float (*hs)[MLP_NH + 4], const float *rs, float (*c6)[6]) {
+    const int l = threadIdx.x & 63;
+    const int r = l & 15, kq = l >> 4;
+    const f32x4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4_t acc[4];
+    // layer 1: [16 nodes x 16 inputs] x [16 x 64]
+    bf16x4_t ah, al;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        short h, lo;
+        bf16_split(xs[r][4 * kq + e], h, lo);
+        ah[e] = h;
+        al[e] = lo;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        bf16x4_t b;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * kq + e;
+            b[e] = k < MLP_NIN ? short(w[(16 * t + r) * MLP_NIN + k]) : short(0);
+        }
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, b, zero, 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, b, acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float b1 = bf16_to_f(w[MLP_OFF_B1 + 16 * t + r]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) hs[4 * kq + v][16 * t + r] = tanhf(acc[t][v] + b1);
+    }
+    __syncthreads();
+    // layers 2 and 3: [16 x 64] x [64 x 64], then [16 x 64] x [64 x 16 (8 used)]
+#pragma unroll
+    for (int layer = 2; layer <= 3; ++layer) {
+        const int nt = layer == 2 ? 4 : 1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = zero;
+#pragma unroll
+        for (int sk = 0; sk < 4; ++sk) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                short h, lo;
+                bf16_split(hs[r][16 * sk + 4 * kq + e], h, lo);
+                ah[e] = h;
+                al[e] = lo;
+            }
+#pragma unroll
+            for (int t = 0; t < nt; ++t) {
+                bf16x4_t b;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * sk + 4 * kq + e;
+                    if (layer == 2) b[e] = short(w[MLP_OFF_W2 + (16 * t + r) * MLP_NH + k]);
+                    else b[e] = r < MLP_NOUT ? short(w[MLP_OFF_W3 + r * MLP_NH + k]) : short(0);
+                }
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, b, acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, b, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();   // every lane has read the previous activations
+        if (layer == 2) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float b2 = bf16_to_f(w[MLP_OFF_B2 + 16 * t + r]);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) hs[4 * kq + v][16 * t + r] = tanhf(acc[t][v] + b2);
+            }
+            __syncthreads();
+        } else if (r < 6) {
+            const float b3 = bf16_to_f(w[MLP_OFF_B3 + r]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int n = 4 * kq + v;
+                c6[n][r] = rs[n] * (cn.tmean[r] + cn.tstd[r] * (acc[0][v] + b3));
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// standardised inputs and density of one D2Q9 node (absolute populations)
+template <class LS>
+__device__ __forceinline__ void closure_inputs(const ClosureNorm &cn, const double *f9, double rho_ref, float *xs16,
+                                               float &rho_out) {
+    double a00 = 0.0;
+#pragma unroll
+    for (int al = 0; al < 9; ++al) a00 += f9[al];
+    // local Kn: Kn at rho_ref, scaled as 1/rho when the relaxation time is
+    const double kn_loc = cn.tau_rho ? cn.kn_ref * rho_ref / a00 : cn.kn_ref;
+    double rho;
+    float x[MLP_NIN];
+    closure_features<LS>(f9, kn_loc, rho, x);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xs16[k] = k < MLP_NIN ? (x[k] - cn.xmean[k]) / cn.xstd[k] : 0.0f;
+    rho_out = float(rho);
+}
+
+// Per step, before the projection pass: closure coefficients of the lifted
+// nodes (the first A.nitems entries of the projection list, low set), one
+// wave per CLOSURE_NB = 16 nodes.
 template <class ST, class LS, class HS>
 __global__ __launch_bounds__(64) void k_closure_infer(const StepArgs A) {
     if constexpr (LS::N == 3 && HS::N == 6) {
-        __shared__ float xs[CLOSURE_NB][MLP_NIN];
-        __shared__ float rs[CLOSURE_NB];
-        __shared__ float h1s[MLP_NH], h2s[MLP_NH];
-        __shared__ float ps[MLP_NOUT][8];
+        __shared__ float xs[16][16];
+        __shared__ float hs[16][MLP_NH + 4];
+        __shared__ float rs[16];
+        __shared__ float c6[16][6];
         const int lane = threadIdx.x;
         const int e0 = blockIdx.x * CLOSURE_NB;
         const int nn = min(CLOSURE_NB, A.nitems - e0);
-        if (lane < nn) {
-            const int e = e0 + lane;
-            const int i = A.items[2 * e], j = A.items[2 * e + 1];
-            double f9[9];
-            load_node_d<ST, LS>(A.self, A.cur ^ 1, i, j, A.rho_shift, f9);
-            double a00 = 0.0;
+        if (lane < 16) {
+            if (lane < nn) {
+                const int e = e0 + lane;
+                const int i = A.items[2 * e], j = A.items[2 * e + 1];
+                double f9[9];
+                load_node_d<ST, LS>(A.self, A.cur ^ 1, i, j, A.rho_shift, f9);
+                closure_inputs<LS>(A.cn, f9, A.ph.rho_ref, xs[lane], rs[lane]);
+            } else {
 #pragma unroll
-            for (int al = 0; al < 9; ++al) a00 += f9[al];
-            // local Kn: Kn at rho_ref, scaled as 1/rho when the relaxation time is
-            const double kn_loc = A.cn.tau_rho ? A.cn.kn_ref * A.ph.rho_ref / a00 : A.cn.kn_ref;
-            double rho;
-            float x[MLP_NIN];
-            closure_features<LS>(f9, kn_loc, rho, x);
-#pragma unroll
-            for (int k = 0; k < MLP_NIN; ++k) xs[lane][k] = (x[k] - A.cn.xmean[k]) / A.cn.xstd[k];
-            rs[lane] = float(rho);
-        }
-        // this lane's weights: hidden unit `lane` of layers 1 and 2, and
-        // eight terms of output lane / 8 of layer 3
-        const uint16_t *w = A.clw;
-        float w1[MLP_NIN], w2[MLP_NH], w3[8];
-#pragma unroll
-        for (int k = 0; k < MLP_NIN; ++k) w1[k] = bf16_to_f(w[lane * MLP_NIN + k]);
-#pragma unroll
-        for (int k = 0; k < MLP_NH; ++k) w2[k] = bf16_to_f(w[MLP_OFF_W2 + lane * MLP_NH + k]);
-        const int oc = lane >> 3, part = lane & 7;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) w3[q] = bf16_to_f(w[MLP_OFF_W3 + oc * MLP_NH + part * 8 + q]);
-        const float b1 = bf16_to_f(w[MLP_OFF_B1 + lane]), b2 = bf16_to_f(w[MLP_OFF_B2 + lane]);
-        const float b3 = lane < MLP_NOUT ? bf16_to_f(w[MLP_OFF_B3 + lane]) : 0.0f;
-        __syncthreads();
-        for (int n = 0; n < nn; ++n) {
-            float s = b1;
-#pragma unroll
-            for (int k = 0; k < MLP_NIN; ++k) s += w1[k] * xs[n][k];
-            h1s[lane] = tanhf(s);
-            __syncthreads();
-            s = b2;
-#pragma unroll
-            for (int k = 0; k < MLP_NH; ++k) s += w2[k] * h1s[k];
-            h2s[lane] = tanhf(s);
-            __syncthreads();
-            float p = 0.0f;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) p += w3[q] * h2s[part * 8 + q];
-            ps[oc][part] = p;
-            __syncthreads();
-            if (lane < 6) {
-                float y = b3;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) y += ps[lane][q];
-                A.clo[6 * (e0 + n) + lane] = rs[n] * (A.cn.tmean[lane] + A.cn.tstd[lane] * y);
+                for (int k = 0; k < 16; ++k) xs[lane][k] = 0.0f;
+                rs[lane] = 0.0f;
             }
-            __syncthreads();
         }
+        __syncthreads();
+        closure_mfma16(A.clw, A.cn, xs, hs, rs, c6);
+        for (int q = lane; q < 6 * nn; q += 64) A.clo[6 * e0 + q] = c6[q / 6][q % 6];
     }
 }
 

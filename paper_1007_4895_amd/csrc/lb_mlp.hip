@@ -107,28 +107,34 @@ __global__ void k_to_bf16(const float *p, uint16_t *out, int n) {
     if (k < n) out[k] = f_to_bf16(p[k]);
 }
 
-// FP32 weights read through bf16 rounding: the inference precision
-struct WRound {
-    const float *p;
-    __device__ float operator()(int i) const { return bf16_to_f(f_to_bf16(p[i])); }
-};
-
-__global__ void k_closure_eval(const float *params, ClosureNorm cn, const double *f9, int64_t n, double *c36,
-                               double rho_ref) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    double f[9];
-    for (int a = 0; a < 9; ++a) f[a] = f9[9 * k + a];
-    float c6[6];
-    closure_coeffs<lbt::VSet<3, 2>>(WRound{params}, cn, f, rho_ref, c6);
-    double *o = c36 + 36 * k;
-    for (int a = 0; a < 36; ++a) o[a] = 0.0;
-    o[3 * 6 + 0] = c6[0];
-    o[0 * 6 + 3] = c6[1];
-    o[3 * 6 + 1] = c6[2];
-    o[1 * 6 + 3] = c6[3];
-    o[4 * 6 + 0] = c6[4];
-    o[0 * 6 + 4] = c6[5];
+// Closure coefficients of n D2Q9 nodes, evaluated as in the lift (the
+// matrix-core network of lb_kernels.hpp), from FP32 weights rounded to bf16
+__global__ __launch_bounds__(64) void k_closure_eval(const uint16_t *w, ClosureNorm cn, const double *f9, int64_t n,
+                                                     double *c36, double rho_ref) {
+    __shared__ float xs[16][16];
+    __shared__ float hs[16][MLP_NH + 4];
+    __shared__ float rs[16];
+    __shared__ float c6[16][6];
+    const int lane = threadIdx.x;
+    const int64_t e0 = int64_t(blockIdx.x) * 16;
+    const int nn = int(min(int64_t(16), n - e0));
+    if (lane < 16) {
+        if (lane < nn) {
+            double f[9];
+            for (int a = 0; a < 9; ++a) f[a] = f9[9 * (e0 + lane) + a];
+            closure_inputs<lbt::VSet<3, 2>>(cn, f, rho_ref, xs[lane], rs[lane]);
+        } else {
+            for (int k = 0; k < 16; ++k) xs[lane][k] = 0.0f;
+            rs[lane] = 0.0f;
+        }
+    }
+    __syncthreads();
+    closure_mfma16(w, cn, xs, hs, rs, c6);
+    for (int q = lane; q < 36 * nn; q += 64) {
+        const int node = q / 36, a = q % 36, k = a / 6, m = a % 6;
+        const int mi = missing_index(k, m);
+        c36[36 * (e0 + node) + a] = mi >= 0 ? double(c6[node][mi]) : 0.0;
+    }
 }
 
 int blocks(int64_t n, int t = 256) { return int((n + t - 1) / t); }
@@ -208,9 +214,16 @@ lb_status lb_closure_eval(const float *params, const float *norm, double kn_ref,
     cn.kn_ref = float(kn_ref);
     cn.tau_rho = tau_rho;
     if (n == 0) return LB_OK;
-    hipLaunchKernelGGL(k_closure_eval, dim3(blocks(n, 64)), dim3(64), 0, reinterpret_cast<hipStream_t>(stream), params,
-                       cn, f9, n, c36, rho_ref);
-    return hipGetLastError() == hipSuccess ? LB_OK : lb_internal_fail(LB_EDEVICE, "closure launch failed");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // the network's bf16 weights, as lb_set_closure makes them for a lattice
+    uint16_t *wb = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&wb), size_t(MLP_NPARAM) * 2, s) != hipSuccess)
+        return lb_internal_fail(LB_ENOMEM, "closure weight buffer");
+    launch_to_bf16(params, wb, s);
+    hipLaunchKernelGGL(k_closure_eval, dim3(unsigned((n + 15) / 16)), dim3(64), 0, s, wb, cn, f9, n, c36, rho_ref);
+    const bool ok = hipGetLastError() == hipSuccess;
+    (void)hipFreeAsync(wb, s);
+    return ok ? LB_OK : lb_internal_fail(LB_EDEVICE, "closure launch failed");
 }
 
 }  // extern "C"
