@@ -928,39 +928,6 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 }
 #undef LB_ST
 
-// Row images (periodic y) and pressure columns of the nodes listed in
-// A.items (i, j, set, 0): node-local, from the freshly written copy.
-template <class ST, class LS, class HS>
-__device__ __forceinline__ void finish_item(const StepArgs &A, const int cur, const int i, const int j,
-                                            const int set) {
-    const int copy = cur ^ 1;
-    if (set == 0) {
-        double f[LS::Q];
-        load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, f);
-        emit_node<ST, LS>(A.self, copy, i, j, A.rho_shift, f, false, A.g, A.ph);
-    } else {
-        double f[HS::Q];
-        load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, f);
-        emit_node<ST, HS>(A.other, copy, i, j, A.rho_shift, f, false, A.g, A.ph);
-    }
-}
-
-template <class ST, class LS, class HS>
-__global__ __launch_bounds__(128) void k_finish(const StepArgs A) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.nitems) return;
-    finish_item<ST, LS, HS>(A, A.cur, A.items[4 * k], A.items[4 * k + 1], A.items[4 * k + 2]);
-}
-
-// batch form: items (i, j, set, l)
-template <class ST, class LS, class HS>
-__global__ __launch_bounds__(128) void k_finish_batch(const BatchArgs B) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= B.nitems) return;
-    finish_item<ST, LS, HS>(B.desc[B.items[4 * k + 3]], B.cur, B.items[4 * k], B.items[4 * k + 1],
-                            B.items[4 * k + 2]);
-}
-
 // One population t of the projection of a source node (set SS, absolute
 // values fs) onto set DD; also returns rho, u of the node.
 // order of the six components a tensor-product D2Q9 lacks at total order 3-4
@@ -1082,6 +1049,52 @@ __device__ void emit_pop(const Buf &b, int copy, int i, int j, double shift, int
         if (i == 0) { put(-1, j, gv); put(-2, j, gv); }
         else { put(g.nx, j, gv); put(g.nx + 1, j, gv); }
     }
+}
+
+// Row images (periodic y) and pressure columns of the nodes listed in
+// A.items (i, j, set, 0): node-local, from the freshly written copy, one
+// thread per (node, population).
+template <class ST, class LS, class HS>
+__device__ __forceinline__ void finish_pop(const StepArgs &A, const int cur, const int i, const int j, const int set,
+                                           const int t) {
+    const int copy = cur ^ 1;
+    double rho, ux, uy;
+    if (set == 0) {
+        if (t >= LS::Q) return;
+        double f[LS::Q];
+        load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, f);
+        moments_d<LS>(f, rho, ux, uy);
+        emit_pop<ST, LS>(A.self, copy, i, j, A.rho_shift, t, f[t], rho, ux, uy, A.g, A.ph);
+    } else {
+        if (t >= HS::Q) return;
+        double f[HS::Q];
+        load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, f);
+        moments_d<HS>(f, rho, ux, uy);
+        emit_pop<ST, HS>(A.other, copy, i, j, A.rho_shift, t, f[t], rho, ux, uy, A.g, A.ph);
+    }
+}
+
+template <class LS, class HS>
+constexpr int finish_qmax() { return LS::Q > HS::Q ? LS::Q : HS::Q; }
+
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_finish(const StepArgs A) {
+    constexpr int QM = finish_qmax<LS, HS>();
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = k / QM;
+    if (e >= A.nitems) return;
+    finish_pop<ST, LS, HS>(A, A.cur, A.items[4 * e], A.items[4 * e + 1], A.items[4 * e + 2], k % QM);
+}
+
+// batch form: items (i, j, set, l)
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_finish_batch(const BatchArgs B) {
+    constexpr int QM = finish_qmax<LS, HS>();
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = k / QM;
+    if (e >= B.nitems) return;
+    finish_pop<ST, LS, HS>(B.desc[B.items[4 * e + 3]], B.cur, B.items[4 * e], B.items[4 * e + 1], B.items[4 * e + 2],
+                           k % QM);
 }
 
 // Hermite-moment projection of the halo-source nodes into the partner set,

@@ -659,7 +659,8 @@ lb_status one_step(lb_lattice *L) {
     if (L->nfin) {
         a.items = L->d_fin;
         a.nitems = L->nfin;
-        L->ks[0]->finish(a, (L->nfin + 127) / 128, L->stream);
+        const int qm = std::max(L->Q[0], L->Q[1]);   // one thread per (node, population)
+        L->ks[0]->finish(a, int((int64_t(L->nfin) * qm + 127) / 128), L->stream);
     }
     if (L->p.iface == LB_IFACE_PAPER)
         L->ks[0]->paper_iface(node_args(L, 0, L->cur ^ 1), L->cur ^ 1, 1, (2 * L->p.nx + 255) / 256, L->stream);
@@ -1449,7 +1450,8 @@ lb_status batch_launch(lb_batch *B, int cur, uint32_t seed) {
     for (auto &K : B->kinds) {
         if (!K.nfin) continue;
         BatchArgs a{B->d_desc[0], K.d_fin, K.nfin, 0, cur, 0, seed};
-        K.ks[0]->finish_batch(a, (K.nfin + 127) / 128, B->stream);
+        const int qm = std::max(K.ks[0]->nS * K.ks[0]->nS, K.ks[1]->nS * K.ks[1]->nS);
+        K.ks[0]->finish_batch(a, int((int64_t(K.nfin) * qm + 127) / 128), B->stream);
     }
     return LB_OK;
 }
