@@ -1004,6 +1004,78 @@ __device__ double project_one(const double *fs, int t, double &rho, double &ux, 
     }
 }
 
+// The ND populations t = tp + ND tq (tp = 0..ND-1) of one target column
+// tq of the projection: the node's coefficients are formed once and each
+// output sums exactly as project_one does (bit-identical results).
+template <class SS, class DD>
+__device__ void project_col(const double *fs, int tq, double *out, double &rho, double &ux, double &uy,
+                            const float *cl6 = nullptr) {
+    using TS = typename SS::T;
+    using TD = typename DD::T;
+    constexpr int NS = SS::N, ND = DD::N;
+    constexpr int NM = NS < ND ? NS : ND;
+    double tt[NS][NM];
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) s += fs[p + NS * q] * TS::he.v[m][q];
+            tt[p][m] = s;
+        }
+    double a[NM][NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int p = 0; p < NS; ++p) s += TS::he.v[k][p] * tt[p][m];
+            a[k][m] = s;
+        }
+    rho = a[0][0];
+    ux = a[1][0] / rho;
+    uy = a[0][1] / rho;
+    if constexpr (SS::N == DD::N && SS::EQ == DD::EQ) {
+#pragma unroll
+        for (int tp = 0; tp < ND; ++tp) out[tp] = fs[tp + ND * tq];
+    } else {
+        double px[ND + 1], py[ND + 1];
+        px[0] = py[0] = 1.0;
+#pragma unroll
+        for (int k = 1; k <= ND; ++k) {
+            px[k] = px[k - 1] * ux;
+            py[k] = py[k - 1] * uy;
+        }
+        double b[ND];
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            double bk = 0.0;
+#pragma unroll
+            for (int m = 0; m < ND; ++m) {
+                double eqd = (k + m <= DD::EQ) ? rho * px[k] * py[m] : 0.0;
+                double neq = 0.0;
+                if (k < NM && m < NM) {
+                    neq = a[k][m] - ((k + m <= SS::EQ) ? rho * px[k] * py[m] : 0.0);
+                } else if (cl6) {
+                    const int mi = missing_index(k, m);
+                    if (mi >= 0) neq = double(cl6[mi]);
+                }
+                bk += (eqd + neq) * TD::hk.v[m][tq];
+            }
+            b[k] = bk;
+        }
+#pragma unroll
+        for (int tp = 0; tp < ND; ++tp) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) s += TD::hk.v[k][tp] * b[k];
+            out[tp] = TD::rule.w[tp] * TD::rule.w[tq] * s;
+        }
+    }
+}
+
 // one population of the order-EQ equilibrium (absolute)
 template <class SS>
 __device__ double feq_one(double rho, double ux, double uy, int t) {
@@ -1101,60 +1173,65 @@ __global__ __launch_bounds__(128) void k_finish_batch(const BatchArgs B) {
 // one thread per (node, target population).  A.items lists (i, j) pairs:
 // the first A.nitems nodes of the low set project into the high set, the
 // next A.chunk nodes of the high set into the low set.
-// population t of the projection of node (i, j): up = low set into the
-// high set (with the learned closure cl6 if given), else high into low
+// target column tq of the projection of node (i, j): up = low set into
+// the high set (with the learned closure cl6 if given), else high into low
 template <class ST, class LS, class HS>
 __device__ __forceinline__ void project_entry(const StepArgs &A, const int cur, const bool up, const int i,
-                                              const int j, const int t, const float *cl6) {
+                                              const int j, const int tq, const float *cl6) {
     const int copy = cur ^ 1;
     double rho, ux, uy;
     if (up) {
-        double fs[LS::Q];
+        double fs[LS::Q], out[HS::N];
         load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, fs);
-        const double v = project_one<LS, HS>(fs, t, rho, ux, uy, cl6);
-        emit_pop<ST, HS>(A.other, copy, i, j, A.rho_shift, t, v, rho, ux, uy, A.g, A.ph);
+        project_col<LS, HS>(fs, tq, out, rho, ux, uy, cl6);
+#pragma unroll
+        for (int tp = 0; tp < HS::N; ++tp)
+            emit_pop<ST, HS>(A.other, copy, i, j, A.rho_shift, tp + HS::N * tq, out[tp], rho, ux, uy, A.g, A.ph);
     } else {
-        double fs[HS::Q];
+        double fs[HS::Q], out[LS::N];
         load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, fs);
-        const double v = project_one<HS, LS>(fs, t, rho, ux, uy);
-        emit_pop<ST, LS>(A.self, copy, i, j, A.rho_shift, t, v, rho, ux, uy, A.g, A.ph);
+        project_col<HS, LS>(fs, tq, out, rho, ux, uy);
+#pragma unroll
+        for (int tp = 0; tp < LS::N; ++tp)
+            emit_pop<ST, LS>(A.self, copy, i, j, A.rho_shift, tp + LS::N * tq, out[tp], rho, ux, uy, A.g, A.ph);
     }
 }
 
+// one thread per (node, target column)
 template <class ST, class LS, class HS>
 __global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n0 = (int64_t)A.nitems * HS::Q, n1 = (int64_t)A.chunk * LS::Q;
+    const int64_t n0 = (int64_t)A.nitems * HS::N, n1 = (int64_t)A.chunk * LS::N;
     if (k < n0) {
-        const int e = int(k / HS::Q), t = int(k % HS::Q);
-        project_entry<ST, LS, HS>(A, A.cur, true, A.items[2 * e], A.items[2 * e + 1], t,
+        const int e = int(k / HS::N), tq = int(k % HS::N);
+        project_entry<ST, LS, HS>(A, A.cur, true, A.items[2 * e], A.items[2 * e + 1], tq,
                                   A.clo ? A.clo + 6 * e : nullptr);
     } else if (k < n0 + n1) {
-        const int e = int((k - n0) / LS::Q) + A.nitems, t = int((k - n0) % LS::Q);
-        project_entry<ST, LS, HS>(A, A.cur, false, A.items[2 * e], A.items[2 * e + 1], t, nullptr);
+        const int e = int((k - n0) / LS::N) + A.nitems, tq = int((k - n0) % LS::N);
+        project_entry<ST, LS, HS>(A, A.cur, false, A.items[2 * e], A.items[2 * e + 1], tq, nullptr);
     }
 }
 
 // batch form: items (i, j, l, 0); the first B.nitems entries project up,
-// the next B.nsplit down
+// the next B.nsplit down; one thread per (node, target column)
 template <class ST, class LS, class HS>
 __global__ __launch_bounds__(128) void k_project_halo_batch(const BatchArgs B) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n0 = (int64_t)B.nitems * HS::Q, n1 = (int64_t)B.nsplit * LS::Q;
-    int e, t;
+    const int64_t n0 = (int64_t)B.nitems * HS::N, n1 = (int64_t)B.nsplit * LS::N;
+    int e, tq;
     bool up;
     if (k < n0) {
-        e = int(k / HS::Q);
-        t = int(k % HS::Q);
+        e = int(k / HS::N);
+        tq = int(k % HS::N);
         up = true;
     } else if (k < n0 + n1) {
-        e = int((k - n0) / LS::Q) + B.nitems;
-        t = int((k - n0) % LS::Q);
+        e = int((k - n0) / LS::N) + B.nitems;
+        tq = int((k - n0) % LS::N);
         up = false;
     } else {
         return;
     }
-    project_entry<ST, LS, HS>(B.desc[B.items[4 * e + 2]], B.cur, up, B.items[4 * e], B.items[4 * e + 1], t,
+    project_entry<ST, LS, HS>(B.desc[B.items[4 * e + 2]], B.cur, up, B.items[4 * e], B.items[4 * e + 1], tq,
                               nullptr);
 }
 

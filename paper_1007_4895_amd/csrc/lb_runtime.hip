@@ -644,11 +644,12 @@ lb_status one_step(lb_lattice *L) {
             down.items = L->d_proj + 2 * L->nproj[0];
             down.nitems = 0;
             down.clo = nullptr;
-            if (L->nproj[0]) L->ks[0]->project_halo(up, int((int64_t(L->nproj[0]) * L->Q[1] + 127) / 128), sl);
+            if (L->nproj[0]) L->ks[0]->project_halo(up, int((int64_t(L->nproj[0]) * L->n[1] + 127) / 128), sl);
             if (L->nproj[1])
-                L->ks[0]->project_halo(down, int((int64_t(L->nproj[1]) * L->Q[0] + 127) / 128), L->stream);
+                L->ks[0]->project_halo(down, int((int64_t(L->nproj[1]) * L->n[0] + 127) / 128), L->stream);
         } else {
-            const int64_t nt = int64_t(L->nproj[0]) * L->Q[1] + int64_t(L->nproj[1]) * L->Q[0];
+            // one thread per (node, target column)
+            const int64_t nt = int64_t(L->nproj[0]) * L->n[1] + int64_t(L->nproj[1]) * L->n[0];
             L->ks[0]->project_halo(a, int((nt + 127) / 128), L->stream);
         }
     }
@@ -1182,7 +1183,7 @@ lb_status lb_change_regions(lb_lattice *L, const int32_t *lo, const int32_t *hi)
         a.clw = L->d_clw;
         a.cn = L->cn;
         L->ks[0]->closure_infer(a, (L->nproj[0] + lbi::CLOSURE_NB - 1) / lbi::CLOSURE_NB, L->stream);
-        L->ks[0]->project_halo(a, int((int64_t(L->nproj[0]) * L->Q[1] + 127) / 128), L->stream);
+        L->ks[0]->project_halo(a, int((int64_t(L->nproj[0]) * L->n[1] + 127) / 128), L->stream);
         HIPCHK(hipGetLastError());
     }
     HIPCHK(hipStreamSynchronize(L->stream));
@@ -1435,7 +1436,7 @@ lb_status batch_launch(lb_batch *B, int cur, uint32_t seed) {
             K.ks[s]->update_batch(a, 8 * K.chunk[s], s ? B->stream : B->side);
         }
     for (auto &K : B->kinds) {
-        const int qh = K.ks[1]->nS * K.ks[1]->nS, ql = K.ks[0]->nS * K.ks[0]->nS;
+        const int qh = K.ks[1]->nS, ql = K.ks[0]->nS;   // one thread per (node, target column)
         if (K.nup) {
             BatchArgs a{B->d_desc[0], K.d_proj, K.nup, 0, cur, 0, seed};
             K.ks[0]->project_batch(a, int((int64_t(K.nup) * qh + 127) / 128), B->side);
