@@ -344,29 +344,6 @@ __device__ void project_d(const double *fs, double *fd, const double *closure) {
     }
 }
 
-// Diffuse reflection at a wall node (Sec. 3.2): rho_W from the populations
-// moving into the wall, the populations leaving the wall set to rho_W S,
-// S = f_eq(rho = 1, u_wall); populations with xi_y = 0 untouched.
-template <class SS>
-__device__ void diffuse_wall_d(double *f, bool top, const Phys &ph) {
-    using TB = typename SS::T;
-    double Sw[SS::Q];
-    const double *uw = top ? ph.uw + 2 : ph.uw;
-    feq_d<SS>(1.0, uw[0], uw[1], Sw);
-    const double nsign = top ? -1.0 : 1.0;
-    double num = 0.0, den = 0.0;
-#pragma unroll
-    for (int a = 0; a < SS::Q; ++a) {
-        double cn = TB::rule.x[a / SS::N] * nsign;
-        if (cn < 0.0) num += -cn * f[a];
-        else if (cn > 0.0) den += cn * Sw[a];
-    }
-    const double rw = num / den;
-#pragma unroll
-    for (int a = 0; a < SS::Q; ++a)
-        if (TB::rule.x[a / SS::N] * nsign > 0.0) f[a] = rw * Sw[a];
-}
-
 // ---------------------------------------------------- node stores (FP64 in)
 template <class ST, class SS>
 __device__ __forceinline__ typename ST::S *plane0(const Buf &b, int copy) {
@@ -928,8 +905,6 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 }
 #undef LB_ST
 
-// One population t of the projection of a source node (set SS, absolute
-// values fs) onto set DD; also returns rho, u of the node.
 // order of the six components a tensor-product D2Q9 lacks at total order 3-4
 __device__ __forceinline__ int missing_index(int k, int m) {
     if (k == 3 && m == 0) return 0;
@@ -941,72 +916,11 @@ __device__ __forceinline__ int missing_index(int k, int m) {
     return -1;
 }
 
-template <class SS, class DD>
-__device__ double project_one(const double *fs, int t, double &rho, double &ux, double &uy,
-                              const float *cl6 = nullptr) {
-    using TS = typename SS::T;
-    using TD = typename DD::T;
-    constexpr int NS = SS::N, ND = DD::N;
-    constexpr int NM = NS < ND ? NS : ND;
-    double tt[NS][NM];
-#pragma unroll
-    for (int p = 0; p < NS; ++p)
-#pragma unroll
-        for (int m = 0; m < NM; ++m) {
-            double s = 0.0;
-#pragma unroll
-            for (int q = 0; q < NS; ++q) s += fs[p + NS * q] * TS::he.v[m][q];
-            tt[p][m] = s;
-        }
-    double a[NM][NM];
-#pragma unroll
-    for (int k = 0; k < NM; ++k)
-#pragma unroll
-        for (int m = 0; m < NM; ++m) {
-            double s = 0.0;
-#pragma unroll
-            for (int p = 0; p < NS; ++p) s += TS::he.v[k][p] * tt[p][m];
-            a[k][m] = s;
-        }
-    rho = a[0][0];
-    ux = a[1][0] / rho;
-    uy = a[0][1] / rho;
-    if constexpr (SS::N == DD::N && SS::EQ == DD::EQ) {
-        return fs[t];
-    } else {
-        double px[ND + 1], py[ND + 1];
-        px[0] = py[0] = 1.0;
-#pragma unroll
-        for (int k = 1; k <= ND; ++k) {
-            px[k] = px[k - 1] * ux;
-            py[k] = py[k - 1] * uy;
-        }
-        const int tp = t % ND, tq = t / ND;
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < ND; ++k) {
-            double b = 0.0;
-#pragma unroll
-            for (int m = 0; m < ND; ++m) {
-                double eqd = (k + m <= DD::EQ) ? rho * px[k] * py[m] : 0.0;
-                double neq = 0.0;
-                if (k < NM && m < NM) {
-                    neq = a[k][m] - ((k + m <= SS::EQ) ? rho * px[k] * py[m] : 0.0);
-                } else if (cl6) {
-                    const int mi = missing_index(k, m);
-                    if (mi >= 0) neq = double(cl6[mi]);
-                }
-                b += (eqd + neq) * TD::hk.v[m][tq];
-            }
-            s += TD::hk.v[k][tp] * b;
-        }
-        return TD::rule.w[tp] * TD::rule.w[tq] * s;
-    }
-}
 
-// The ND populations t = tp + ND tq (tp = 0..ND-1) of one target column
-// tq of the projection: the node's coefficients are formed once and each
-// output sums exactly as project_one does (bit-identical results).
+// Hermite-moment projection of one source node (set SS, absolute values
+// fs) onto set DD (Sec. 2.2 in moment form), for the ND populations
+// t = tp + ND tq of one target column tq; also returns rho, u of the node.
+// The node's coefficients are formed once per column.
 template <class SS, class DD>
 __device__ void project_col(const double *fs, int tq, double *out, double &rho, double &ux, double &uy,
                             const float *cl6 = nullptr) {

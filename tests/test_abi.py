@@ -89,3 +89,26 @@ def test_default_time_step_matches_gauss_hermite_rule(lbmod, oracle):
         assert L.lb_workspace_bytes(C.byref(p)) > 0
         p = lbmod.make_params(nx=8, ny=64, kn=1.0, n_low=n, n_high=n, eq_low=2, dt=2 * want * (1 + 1e-9))
         assert L.lb_workspace_bytes(C.byref(p)) == 0
+
+
+def test_null_arguments_are_rejected(lbmod):
+    # entry points validate their pointers before touching the device
+    L = lbmod.lib()
+    v = C.c_void_p
+    EINVAL = lbmod.LB_EINVAL
+    out = v()
+    assert L.lb_batch_create(None, 0, None, C.byref(out)) == EINVAL
+    assert L.lb_batch_step(None, 1) == EINVAL
+    assert L.lb_batch_set_graph(None, 4) == EINVAL
+    assert L.lb_batch_autotune(None, 5, None) == EINVAL
+    assert L.lb_set_merged_update(None, 1) == EINVAL
+    assert L.lb_set_concurrency(None, 1) == EINVAL
+    assert L.lb_set_closure(None, None, None) == EINVAL
+    assert L.lb_closure_samples(None, None, 0, 0.01, None, None, None) == EINVAL
+    assert L.lb_mlp_forward(None, None, None, 0, None, None) == EINVAL
+    assert L.lb_mlp_loss_grad(None, None, None, None, 1, None, None, None, None) == EINVAL
+    assert L.lb_mlp_adam(None, None, None, None, 1, 1e-3, None) == EINVAL
+    assert L.lb_mlp_param_count() == 64 * 10 + 64 + 64 * 64 + 64 + 8 * 64 + 8
+    assert L.lb_mlp_workspace_bytes(1000) >= 4 * 1000 * (2 * 64 + 2 * 8 + 2 * 64 + 1)
+    assert L.lb_set_work_shape(None, None, None) == EINVAL
+    assert "bad argument" in L.lb_last_error().decode() or "null" in L.lb_last_error().decode()
