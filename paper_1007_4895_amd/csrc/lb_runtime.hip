@@ -1316,8 +1316,6 @@ struct lb_batch {
     struct Kind {
         const lbk::KernelSet *ks[2];   // the pair's kernels, self = low / high set
         std::vector<int> members;      // lattice indices
-        int32_t *d_items[2] = {nullptr, nullptr};
-        int nitems[2] = {0, 0}, chunk[2] = {0, 0};
         int32_t *d_fin = nullptr;
         int nfin = 0;
         int32_t *d_proj = nullptr;
@@ -1325,9 +1323,18 @@ struct lb_batch {
     };
     std::vector<lb_lattice *> lat;
     std::vector<int64_t> gen;          // region generation of each lattice at the last build
+    // update work items grouped by velocity set: the update of a set does
+    // not depend on its partner, so one launch serves the set in every pair
+    struct SetGroup {
+        const lbk::KernelSet *ks;      // any kernel set whose self set is this one
+        int n, eq;
+        int32_t *d_items = nullptr;    // (i0, j0, j1, side * nlat + lattice)
+        int nitems = 0, chunk = 0;
+    };
     std::vector<Kind> kinds;
+    std::vector<SetGroup> groups;
     hipStream_t stream;
-    StepArgs *d_desc[2];               // per lattice, self = low set / high set
+    StepArgs *d_desc[2];               // per lattice, self = low set / high set (one allocation, high after low)
     int strip[2];                      // rows per work item (0 = automatic)
     int cur;
     int seg;                           // steps per captured graph (0 = direct launches)
@@ -1366,15 +1373,18 @@ lb_status batch_build(lb_batch *B) {
     batch_drop_graphs(B);
     std::vector<std::pair<int, int>> runs;
     std::vector<int> runcol;
+    const int nl = int(B->lat.size());
+    std::vector<std::vector<int32_t>> gv(B->groups.size());
     for (auto &K : B->kinds) {
         for (int s = 0; s < 2; ++s) {
+            size_t g = 0;
+            while (g < B->groups.size() && !(B->groups[g].n == K.ks[s]->nS && B->groups[g].eq == K.ks[s]->eqS)) ++g;
             int64_t rows = 0;
             for (int l : K.members) rows += set_runs(B->lat[l], s, runs, runcol);
             const int strip = B->strip[s] > 0 ? B->strip[s] : auto_strip(rows);
-            // items ordered by lattice, column group and row, cut into 8
-            // contiguous slabs (one per XCD through the kernel's mapping) so
-            // neighbouring strips of one lattice share an L2
-            std::vector<int32_t> v;
+            // items ordered by lattice, column group and row (cut into XCD
+            // slabs below) so neighbouring strips of one lattice share an L2
+            std::vector<int32_t> &v = gv[g];
             for (int l : K.members) {
                 set_runs(B->lat[l], s, runs, runcol);
                 // a lattice at most 28 columns wide packs 64 / (nx + 4) lane
@@ -1387,16 +1397,22 @@ lb_status batch_build(lb_batch *B) {
                         v.push_back(ng >= 2 ? -strip : runcol[r]);
                         v.push_back(j);
                         v.push_back(std::min(j + span, runs[r].second));
-                        v.push_back(l);
+                        v.push_back(s * nl + l);
                     }
             }
-            const int n = int(v.size() / 4);
-            K.chunk[s] = (n + 7) / 8;
-            v.resize(size_t(8) * K.chunk[s] * 4, 0);   // padding items are empty (j0 = j1)
-            K.nitems[s] = 8 * K.chunk[s];
-            lb_status st = upload_list(v, K.d_items[s], B->stream);
-            if (st != LB_OK) return st;
         }
+    }
+    for (size_t g = 0; g < B->groups.size(); ++g) {
+        auto &G = B->groups[g];
+        std::vector<int32_t> &v = gv[g];
+        const int n = int(v.size() / 4);
+        G.chunk = (n + 7) / 8;   // 8 contiguous slabs, one per XCD through the kernel's mapping
+        v.resize(size_t(8) * G.chunk * 4, 0);   // padding items are empty (j0 = j1)
+        G.nitems = 8 * G.chunk;
+        lb_status st = upload_list(v, G.d_items, B->stream);
+        if (st != LB_OK) return st;
+    }
+    for (auto &K : B->kinds) {
         std::vector<int32_t> fin, up, down, f1, p1;
         for (int l : K.members) {
             lb_lattice *L = B->lat[l];
@@ -1423,31 +1439,41 @@ lb_status batch_build(lb_batch *B) {
     return LB_OK;
 }
 
-// the launches of one step of every lattice (source copy cur): the low
-// sets' updates and their projections into the high sets run on the side
-// stream, the high sets' on the batch stream (as in a single lattice's step)
-lb_status batch_launch(lb_batch *B, int cur, uint32_t seed) {
+// the launches of one step of every lattice (source copy cur): one update
+// launch per velocity set (all lattices, both roles), alternating between
+// the batch stream and the side stream; then one projection launch per set
+// pair, alternating likewise; the finish pass after both streams join
+lb_status batch_fork(lb_batch *B) {
     HIPCHK(hipEventRecord(B->efork, B->stream));
     HIPCHK(hipStreamWaitEvent(B->side, B->efork, 0));
-    for (auto &K : B->kinds)
-        for (int s = 0; s < 2; ++s) {
-            if (!K.chunk[s]) continue;
-            BatchArgs a{B->d_desc[s], K.d_items[s], K.nitems[s], K.chunk[s], cur, 0, seed};
-            K.ks[s]->update_batch(a, 8 * K.chunk[s], s ? B->stream : B->side);
-        }
-    for (auto &K : B->kinds) {
-        const int qh = K.ks[1]->nS, ql = K.ks[0]->nS;   // one thread per (node, target column)
-        if (K.nup) {
-            BatchArgs a{B->d_desc[0], K.d_proj, K.nup, 0, cur, 0, seed};
-            K.ks[0]->project_batch(a, int((int64_t(K.nup) * qh + 127) / 128), B->side);
-        }
-        if (K.ndown) {
-            BatchArgs a{B->d_desc[0], K.d_proj + 4 * K.nup, 0, 0, cur, K.ndown, seed};
-            K.ks[0]->project_batch(a, int((int64_t(K.ndown) * ql + 127) / 128), B->stream);
-        }
-    }
+    return LB_OK;
+}
+
+lb_status batch_joinside(lb_batch *B) {
     HIPCHK(hipEventRecord(B->ejoin, B->side));
     HIPCHK(hipStreamWaitEvent(B->stream, B->ejoin, 0));
+    return LB_OK;
+}
+
+lb_status batch_launch(lb_batch *B, int cur, uint32_t seed) {
+    lb_status st = batch_fork(B);
+    if (st != LB_OK) return st;
+    for (size_t g = 0; g < B->groups.size(); ++g) {
+        auto &G = B->groups[g];
+        if (!G.chunk) continue;
+        BatchArgs a{B->d_desc[0], G.d_items, G.nitems, G.chunk, cur, 0, seed};
+        G.ks->update_batch(a, 8 * G.chunk, g & 1 ? B->side : B->stream);
+    }
+    if ((st = batch_joinside(B)) != LB_OK || (st = batch_fork(B)) != LB_OK) return st;
+    for (size_t k = 0; k < B->kinds.size(); ++k) {
+        auto &K = B->kinds[k];
+        if (!(K.nup + K.ndown)) continue;
+        // one thread per (node, target column)
+        const int64_t nt = int64_t(K.nup) * K.ks[1]->nS + int64_t(K.ndown) * K.ks[0]->nS;
+        BatchArgs a{B->d_desc[0], K.d_proj, K.nup, 0, cur, K.ndown, seed};
+        K.ks[0]->project_batch(a, int((nt + 127) / 128), k & 1 ? B->side : B->stream);
+    }
+    if ((st = batch_joinside(B)) != LB_OK) return st;
     for (auto &K : B->kinds) {
         if (!K.nfin) continue;
         BatchArgs a{B->d_desc[0], K.d_fin, K.nfin, 0, cur, 0, seed};
@@ -1585,12 +1611,23 @@ lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stre
             B->kinds.push_back(K);
         }
         B->kinds[k].members.push_back(l);
+        for (int s = 0; s < 2; ++s) {
+            size_t g = 0;
+            while (g < B->groups.size() && !(B->groups[g].n == L->ks[s]->nS && B->groups[g].eq == L->ks[s]->eqS)) ++g;
+            if (g == B->groups.size()) {
+                lb_batch::SetGroup G;
+                G.ks = L->ks[s];
+                G.n = L->ks[s]->nS;
+                G.eq = L->ks[s]->eqS;
+                B->groups.push_back(G);
+            }
+        }
     }
-    for (int s = 0; s < 2; ++s) {
-        if (hipMalloc(&B->d_desc[s], sizeof(StepArgs) * n) != hipSuccess) return bail(fail(LB_ENOMEM, "descriptor table"));
+    if (hipMalloc(&B->d_desc[0], sizeof(StepArgs) * 2 * n) != hipSuccess) return bail(fail(LB_ENOMEM, "descriptor table"));
+    B->d_desc[1] = B->d_desc[0] + n;
+    for (int s = 0; s < 2; ++s)
         if (hipMemcpy(B->d_desc[s], desc[s].data(), sizeof(StepArgs) * n, hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(LB_EDEVICE, "descriptor upload failed"));
-    }
     if (hipEventCreateWithFlags(&B->ev, hipEventDisableTiming) != hipSuccess || hipEventCreate(&B->t0) != hipSuccess ||
         hipEventCreate(&B->t1) != hipSuccess || hipEventCreateWithFlags(&B->efork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&B->ejoin, hipEventDisableTiming) != hipSuccess)
@@ -1609,13 +1646,12 @@ void lb_batch_destroy(lb_batch *B) {
     else (void)hipDeviceSynchronize();
     batch_drop_graphs(B);
     for (auto &K : B->kinds) {
-        for (int s = 0; s < 2; ++s)
-            if (K.d_items[s]) (void)hipFree(K.d_items[s]);
         if (K.d_fin) (void)hipFree(K.d_fin);
         if (K.d_proj) (void)hipFree(K.d_proj);
     }
-    for (int s = 0; s < 2; ++s)
-        if (B->d_desc[s]) (void)hipFree(B->d_desc[s]);
+    for (auto &G : B->groups)
+        if (G.d_items) (void)hipFree(G.d_items);
+    if (B->d_desc[0]) (void)hipFree(B->d_desc[0]);
     if (B->side) {
         (void)hipStreamSynchronize(B->side);
         (void)hipStreamDestroy(B->side);
@@ -1706,7 +1742,8 @@ lb_status lb_batch_autotune(lb_batch *B, int32_t steps, int32_t rows_out[2]) {
 lb_status lb_batch_info(const lb_batch *B, int64_t *nodes, int32_t *launches_per_step, int32_t *kinds) {
     if (!B) return fail(LB_EINVAL, "null batch");
     int nl = 0;
-    for (auto &K : B->kinds) nl += (K.chunk[0] > 0) + (K.chunk[1] > 0) + (K.nup + K.ndown > 0) + (K.nfin > 0);
+    for (auto &G : B->groups) nl += G.chunk > 0;
+    for (auto &K : B->kinds) nl += (K.nup + K.ndown > 0) + (K.nfin > 0);
     if (nodes) *nodes = B->nodes;
     if (launches_per_step) *launches_per_step = nl;
     if (kinds) *kinds = int32_t(B->kinds.size());
