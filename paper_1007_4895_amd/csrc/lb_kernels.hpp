@@ -28,6 +28,19 @@
 #include "lb_internal.hpp"
 #include "lb_tables.hpp"
 
+// waves per block of the D2Q36 update (each evolves 6 / LB_SPLIT36 of the
+// y-abscissae) and the occupancy it is compiled for, on its own and merged
+// with D2Q9 items or in a batch (measured best: 5 and 4 waves per SIMD)
+#ifndef LB_SPLIT36
+#define LB_SPLIT36 3
+#endif
+#ifndef LB_WAVES36
+#define LB_WAVES36 5
+#endif
+#ifndef LB_WAVES36_PAIR
+#define LB_WAVES36_PAIR 4
+#endif
+
 namespace lbk {
 
 using namespace lbi;
@@ -451,7 +464,7 @@ __device__ void finish_node(const Buf &self, const Buf &other, int copy, int i, 
 // D' = sum_leaving |xi_y| S' and n' the flux of the stored values, so no
 // large quantities cancel in FP32.
 template <class SS>
-constexpr int update_split() { return SS::Q == 36 ? 3 : SS::Q == 16 ? 2 : 1; }
+constexpr int update_split() { return SS::Q == 36 ? LB_SPLIT36 : SS::Q == 16 ? 2 : 1; }
 
 template <class T, int SPLIT>
 __device__ __forceinline__ T (*lds_moments())[3][SPLIT][64] {
@@ -466,7 +479,10 @@ __device__ __forceinline__ T (*lds_wall())[SPLIT][64] {
 
 // occupancy the compiler must fit the update kernel into (waves per SIMD)
 template <class SS>
-constexpr int update_waves() { return SS::Q == 36 ? 4 : SS::Q == 16 ? 4 : 6; }
+constexpr int update_waves() { return SS::Q == 36 ? LB_WAVES36 : SS::Q == 16 ? 4 : 6; }
+// the same for the merged and batched update kernels (more code paths)
+template <class SS>
+constexpr int pair_waves() { return SS::Q == 36 ? LB_WAVES36_PAIR : update_waves<SS>(); }
 
 template <class ST, class SS, class OO, int WV, bool NW = false>
 __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
@@ -491,6 +507,11 @@ __device__ __forceinline__ void update_item(const StepArgs &A, const int cur, co
     if constexpr (SPLIT > 2) {
         if (wv == 2) update_rows<ST, SS, OO, 2, NW>(A, cur, seed, i0, j0, j1, lane, S);
     }
+    if constexpr (SPLIT > 3) {
+        if (wv == 3) update_rows<ST, SS, OO, 3, NW>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 4) update_rows<ST, SS, OO, 4, NW>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 5) update_rows<ST, SS, OO, 5, NW>(A, cur, seed, i0, j0, j1, lane, S);
+    }
 }
 
 template <class ST, class SS, class OO>
@@ -512,9 +533,10 @@ void k_update(const StepArgs A) {
 // item, as k_update), the rest give each of their SPLIT waves its own
 // D2Q9 item.  The two sets touch disjoint buffers, and one launch lets
 // their waves share the machine instead of running back to back.
+
 template <class ST, class LS, class HS>
 __global__ __launch_bounds__(64 * update_split<HS>())
-__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : update_waves<HS>())))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : pair_waves<HS>())))
 void k_update_pair(const StepArgs L, const StepArgs H, const int nb_h) {
     if constexpr (update_split<LS>() == 1) {
         constexpr int SPLIT = update_split<HS>();
@@ -545,7 +567,7 @@ void k_update_pair(const StepArgs L, const StepArgs H, const int nb_h) {
 // lattices of a batch step together, so the copy parity is the launch's.
 template <class ST, class SS, class OO>
 __global__ __launch_bounds__(64 * update_split<SS>())
-__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : update_waves<SS>())))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : pair_waves<SS>())))
 void k_update_batch(const BatchArgs B) {
     const int b = blockIdx.x;
     const int it = (b & 7) * B.chunk + (b >> 3);
