@@ -175,6 +175,16 @@ __device__ __forceinline__ double nbr(double src) {
     return dpp<CTRL>(src, src);
 }
 
+// a wave-uniform value, made known as such to the compiler
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t(uint64_t(lo) | (uint64_t(hi) << 32));
+}
+__device__ __forceinline__ void *uniform(char *p) {
+    return reinterpret_cast<void *>(uniform(int64_t(reinterpret_cast<uintptr_t>(p))));
+}
+
 // minmod(a, b) = median(a, b, 0)
 __device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 __device__ __forceinline__ double minmod(double a, double b) {
@@ -631,15 +641,18 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     // the wave-uniform offset of (population, row) in a scalar register.
     // Lanes that must not store get an offset past the end of the buffer,
     // which the hardware turns into a dropped store (or a zero load).
+    // (the lattice's arguments are wave-uniform; a batch reads them from a
+    // device table, so they are declared uniform here: the descriptor and
+    // the scalar offsets must live in scalar registers)
     constexpr unsigned EB = sizeof(SV);
-    const int64_t P = A.self.plane;
-    const int64_t pitch = A.self.pitch;
-    const int64_t rb = A.self.rowbase - 2;
+    const int64_t P = uniform(A.self.plane);
+    const int64_t pitch = uniform(int64_t(A.self.pitch));
+    const int64_t rb = uniform(int64_t(A.self.rowbase - 2));
     const unsigned nbytes = unsigned(int64_t(Q) * P * EB);
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void *)A.self.base[cur], 0, int(nbytes), 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(uniform(A.self.base[cur]), 0, int(nbytes), 0x00020000);
     const __amdgpu_buffer_rsrc_t rd =
-        __builtin_amdgcn_make_buffer_rsrc((void *)A.self.base[cur ^ 1], 0, int(nbytes), 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(uniform(A.self.base[cur ^ 1]), 0, int(nbytes), 0x00020000);
     const unsigned OOB = nbytes;
     const unsigned vl = unsigned(min(max(col, -2), nx + 1) + 2) * EB;
 #define LB_SOFF(a, j) unsigned(((int64_t)(a) * P + rb + (int64_t)((j) + 2) * pitch) * EB)
