@@ -37,9 +37,6 @@ struct Inst {
             hipLaunchKernelGGL((k_update_pair<ST, S, O>), dim3(nb_h + nb_l), dim3(64 * update_split<O>()), 0, s, l, h,
                                nb_h);
     }
-    static void update_batch(const BatchArgs &a, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_update_batch<ST, S, O>), dim3(grid), dim3(64 * update_split<S>()), 0, s, a);
-    }
     static void finish_batch(const BatchArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_finish_batch<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
     }
@@ -98,7 +95,6 @@ struct Inst {
         k.closure_samples = &closure_samples;
         k.update_pair = update_split<S>() == 1 ? &update_pair : nullptr;
         k.pair_split = update_split<O>();
-        k.update_batch = &update_batch;
         k.finish_batch = &finish_batch;
         k.project_batch = &project_batch;
         k.update_kernel = reinterpret_cast<const void *>(&k_update<ST, S, O>);
@@ -106,7 +102,19 @@ struct Inst {
     }
 };
 
+template <class ST, int E6, int E4>
+struct MultiInst {
+    static void update(const BatchMulti &m, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_update_multi<ST, lbt::VSet<6, E6>, lbt::VSet<4, E4>>), dim3(grid), dim3(192), 0, s, m);
+    }
+    static void project(const BatchMulti &m, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_project_multi<ST, lbt::VSet<6, E6>, lbt::VSet<4, E4>>), dim3(grid), dim3(128), 0, s, m);
+    }
+    static MultiSet make() { return MultiSet{E6, E4, &update, &project}; }
+};
+
 }  // namespace lbk
 
+#define LB_MULTI(ST, e6, e4) lbk::MultiInst<ST, e6, e4>::make()
 #define LB_PAIR(ST, SID, n1, e1, n2, e2) \
     lbk::Inst<ST, lbt::VSet<n1, e1>, lbt::VSet<n2, e2>>::make(SID)

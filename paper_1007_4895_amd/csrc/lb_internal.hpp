@@ -97,6 +97,21 @@ struct BatchArgs {
     uint32_t seed;          // per-step seed of stochastic rounding (bf16 storage)
 };
 
+// One launch serving every velocity set (update) or every set pair
+// (projection) of a batch: three slots of work items, each with its own item
+// list, taking the blocks [start[s], start[s + 1]).  Update slots are the
+// sets D2Q36, D2Q16, D2Q9; projection slots the pairs D2Q9/D2Q36,
+// D2Q16/D2Q36, D2Q9/D2Q16.
+struct BatchMulti {
+    const StepArgs *desc;       // device: per lattice and side, as for BatchArgs
+    const int32_t *items[3];    // device item lists (NULL for an empty slot)
+    int32_t nitems[3];          // update: items; projection: entries projecting up
+    int32_t nsplit[3];          // update: items per XCD slot; projection: entries projecting down
+    int32_t start[4];           // first block of each slot; start[3] = blocks in the launch
+    int32_t cur;                // source copy of every lattice
+    uint32_t seed;              // per-step seed of stochastic rounding (bf16 storage)
+};
+
 // Arguments of the non-step kernels (one thread per node).
 struct NodeArgs {
     Geo g;

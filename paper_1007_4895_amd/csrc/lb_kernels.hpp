@@ -572,23 +572,55 @@ void k_update_pair(const StepArgs L, const StepArgs H, const int nb_h) {
     }
 }
 
-// The same update for a batch of independent lattices in one launch: item
-// (i0, j0, j1, l) belongs to lattice l, whose arguments are B.desc[l]; the
-// lattices of a batch step together, so the copy parity is the launch's.
-template <class ST, class SS, class OO>
-__global__ __launch_bounds__(64 * update_split<SS>())
-__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : pair_waves<SS>())))
-void k_update_batch(const BatchArgs B) {
-    const int b = blockIdx.x;
-    const int it = (b & 7) * B.chunk + (b >> 3);
-    if (it >= B.nitems) return;
-    const int i0 = B.items[4 * it], j0 = B.items[4 * it + 1], j1 = B.items[4 * it + 2];
-    const int l = B.items[4 * it + 3];
+// The update of a batch of independent lattices, every velocity set in one
+// launch.  Item (i0, j0, j1, l) belongs to lattice (and side) l, whose
+// arguments are M.desc[l]; the lattices of a batch step together, so the
+// copy parity is the launch's.  Blocks have three waves: a D2Q36 item takes
+// a whole block, a D2Q16 item two of its waves (the third leaves at once: a
+// barrier waits only for the waves still running), and a D2Q9 item a single
+// wave, three to a block (S36 and S16 are the D2Q36 and D2Q16 sets of the
+// batch, of their equilibrium orders).  Within each slot the blocks are
+// mapped to items XCD by XCD as in the single-lattice kernels (slot starts
+// are multiples of 8).
+template <class ST, class SS>
+__device__ __forceinline__ void batch_item(const BatchMulti &M, const int slot, const int it) {
+    if (it >= M.nitems[slot]) return;
+    const int32_t *e = M.items[slot] + 4 * it;
+    const int i0 = __builtin_amdgcn_readfirstlane(e[0]);
+    const int j0 = __builtin_amdgcn_readfirstlane(e[1]);
+    const int j1 = __builtin_amdgcn_readfirstlane(e[2]);
+    const int l = __builtin_amdgcn_readfirstlane(e[3]);
     if (j0 >= j1) return;   // padding item
+    // the table is read through the constant address space: the lattice's
+    // arguments are then scalar loads, as they are for a single lattice
+    // (through a generic pointer the compiler cannot rule out that the
+    // kernel's own stores change them, and reloads them per lane)
+    const StepArgs &A = *(const StepArgs *)((const __attribute__((address_space(4))) StepArgs *)M.desc + l);
     // a negative first column marks a narrow lattice's item: -i0 rows per
     // lane group
-    if (i0 < 0) update_item<ST, SS, OO, true>(B.desc[l], B.cur, B.seed, 0, j0, j1, -i0);
-    else update_item<ST, SS, OO>(B.desc[l], B.cur, B.seed, i0, j0, j1);
+    if (i0 < 0) update_item<ST, SS, SS, true>(A, M.cur, M.seed, 0, j0, j1, -i0);
+    else update_item<ST, SS, SS>(A, M.cur, M.seed, i0, j0, j1);
+}
+
+template <class ST, class S36, class S16>
+__global__ __launch_bounds__(192)
+__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : LB_WAVES36_PAIR)))
+void k_update_multi(const BatchMulti M) {
+    using S9 = lbt::VSet<3, 2>;
+    static_assert(update_split<S36>() == 3 && update_split<S16>() == 2 && update_split<S9>() == 1,
+                  "three-wave blocks");
+    const int b = blockIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+    if (b < M.start[1]) {
+        batch_item<ST, S36>(M, 0, (b & 7) * M.nsplit[0] + (b >> 3));
+    } else if (b < M.start[2]) {
+        const int bl = b - M.start[1];
+        if (w < 2) batch_item<ST, S16>(M, 1, (bl & 7) * M.nsplit[1] + (bl >> 3));
+    } else {
+        const int bl = b - M.start[2];
+        const int pos = 3 * (bl >> 3) + w;
+        if (pos < M.nsplit[2]) batch_item<ST, S9>(M, 2, (bl & 7) * M.nsplit[2] + pos);
+    }
 }
 
 // store of an updated value of population a in row j: stochastically
@@ -619,7 +651,11 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     constexpr int q0 = WV * NQ;
     constexpr int wv = WV;
     static_assert(N % SPLIT == 0, "split must divide the abscissae");
-    const Geo &g = A.g;
+    // a copy, read once up front: a batch's lattice arguments come from a
+    // device table, and a field first read under a per-lane condition
+    // (e.g. ny in the ownership test) would otherwise be reloaded there and
+    // merged into a per-lane register
+    const Geo g = A.g;
     const int nx = g.nx;
     // narrow lattices: lane group gl of nx + 4 lanes (2 halo columns each
     // side) marches its own rows [jl0, jl1); wide: one group, rows [j0, j1)
@@ -1161,12 +1197,14 @@ __global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
     }
 }
 
-// batch form: items (i, j, l, 0); the first B.nitems entries project up,
-// the next B.nsplit down; one thread per (node, target column)
+// batch form: items (i, j, l, 0) of lattice l, whose arguments (self = low
+// set) are desc[l]; the first nup entries project up, the next ndown down;
+// one thread per (node, target column), k counted from the slot's first
+// block
 template <class ST, class LS, class HS>
-__global__ __launch_bounds__(128) void k_project_halo_batch(const BatchArgs B) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n0 = (int64_t)B.nitems * HS::N, n1 = (int64_t)B.nsplit * LS::N;
+__device__ __forceinline__ void project_batch_entry(const StepArgs *desc, const int32_t *items, const int nup,
+                                                    const int ndown, const int cur, const int64_t k) {
+    const int64_t n0 = (int64_t)nup * HS::N, n1 = (int64_t)ndown * LS::N;
     int e, tq;
     bool up;
     if (k < n0) {
@@ -1174,14 +1212,36 @@ __global__ __launch_bounds__(128) void k_project_halo_batch(const BatchArgs B) {
         tq = int(k % HS::N);
         up = true;
     } else if (k < n0 + n1) {
-        e = int((k - n0) / LS::N) + B.nitems;
+        e = int((k - n0) / LS::N) + nup;
         tq = int((k - n0) % LS::N);
         up = false;
     } else {
         return;
     }
-    project_entry<ST, LS, HS>(B.desc[B.items[4 * e + 2]], B.cur, up, B.items[4 * e], B.items[4 * e + 1], tq,
-                              nullptr);
+    project_entry<ST, LS, HS>(desc[items[4 * e + 2]], cur, up, items[4 * e], items[4 * e + 1], tq, nullptr);
+}
+
+// one set pair per launch (pairs outside the three slots of k_project_multi)
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_project_halo_batch(const BatchArgs B) {
+    project_batch_entry<ST, LS, HS>(B.desc, B.items, B.nitems, B.nsplit, B.cur,
+                                    (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// the pairs D2Q9/D2Q36, D2Q16/D2Q36 and D2Q9/D2Q16 in one launch
+template <class ST, class S36, class S16>
+__global__ __launch_bounds__(128) void k_project_multi(const BatchMulti M) {
+    using S9 = lbt::VSet<3, 2>;
+    const int b = blockIdx.x;
+    const int t = threadIdx.x;
+    if (b < M.start[1])
+        project_batch_entry<ST, S9, S36>(M.desc, M.items[0], M.nitems[0], M.nsplit[0], M.cur, (int64_t)b * 128 + t);
+    else if (b < M.start[2])
+        project_batch_entry<ST, S16, S36>(M.desc, M.items[1], M.nitems[1], M.nsplit[1], M.cur,
+                                          (int64_t)(b - M.start[1]) * 128 + t);
+    else
+        project_batch_entry<ST, S9, S16>(M.desc, M.items[2], M.nitems[2], M.nsplit[2], M.cur,
+                                         (int64_t)(b - M.start[2]) * 128 + t);
 }
 
 // ------------------------------------------------------- learned closure

@@ -34,15 +34,25 @@ struct KernelSet {
     NodeFn closure_samples; // training samples from an all-high run (self = high set)
     PairFn update_pair;     // NULL unless the low set is D2Q9
     int pair_split;         // waves per block of update_pair (the high set's split)
-    BatchFn update_batch;   // batched forms (finish / projection: self = low set)
-    BatchFn finish_batch;
+    BatchFn finish_batch;   // batched forms (self = low set)
     BatchFn project_batch;
     const void *update_kernel;   // the __global__ symbol (for attribute queries)
+};
+
+// Kernels serving every velocity set (update) or set pair (projection) of a
+// batch in one launch, for the sets D2Q36 of order eq6, D2Q16 of order eq4
+// and D2Q9 (order 2).
+using MultiFn = void (*)(const lbi::BatchMulti &, int grid, hipStream_t);
+struct MultiSet {
+    int eq6, eq4;
+    MultiFn update, project;
 };
 
 struct Registry {
     const KernelSet *sets;
     int count;
+    const MultiSet *multi;
+    int nmulti;
 };
 
 // error reporting shared by the runtime's translation units

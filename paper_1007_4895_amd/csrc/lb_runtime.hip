@@ -1307,10 +1307,11 @@ lb_status lb_kernel_times(lb_lattice *L, double *ms_high, int64_t *n_high, doubl
 }  // extern "C"
 
 // ------------------------------------------------------------------ batches
-// Many independent lattices stepped together: per step, one launch per
-// kernel and velocity-set pair covers the work items of every lattice of
-// that pair (each item names its lattice, whose arguments sit in a device
-// descriptor table), optionally replayed from a captured HIP graph.
+// Many independent lattices stepped together: per step, one update launch
+// covers the work items of every lattice and velocity set, and one
+// projection launch every set pair (each item names its lattice, whose
+// arguments sit in a device descriptor table), all on one stream,
+// optionally replayed from a captured HIP graph.
 
 struct lb_batch {
     struct Kind {
@@ -1320,19 +1321,29 @@ struct lb_batch {
         int nfin = 0;
         int32_t *d_proj = nullptr;
         int nup = 0, ndown = 0;
+        bool merged = false;           // projected by a merged launch (else by one of its own)
     };
     std::vector<lb_lattice *> lat;
     std::vector<int64_t> gen;          // region generation of each lattice at the last build
     // update work items grouped by velocity set: the update of a set does
     // not depend on its partner, so one launch serves the set in every pair
     struct SetGroup {
-        const lbk::KernelSet *ks;      // any kernel set whose self set is this one
         int n, eq;
         int32_t *d_items = nullptr;    // (i0, j0, j1, side * nlat + lattice)
         int nitems = 0, chunk = 0;
     };
     std::vector<Kind> kinds;
     std::vector<SetGroup> groups;
+    // merged launches: per registered kernel pair, the groups in its update
+    // slots (D2Q36, D2Q16, D2Q9) and the kinds in its projection slots
+    // (D2Q9/D2Q36, D2Q16/D2Q36, D2Q9/D2Q16), -1 where empty
+    struct Plan {
+        const lbk::MultiSet *ms;
+        int group[3];
+        int kind[3];
+    };
+    std::vector<Plan> plans;
+    lbk::Registry reg;
     hipStream_t stream;
     StepArgs *d_desc[2];               // per lattice, self = low set / high set (one allocation, high after low)
     int strip[2];                      // rows per work item (0 = automatic)
@@ -1341,8 +1352,6 @@ struct lb_batch {
     hipGraph_t graph[2];               // one per starting copy parity
     hipGraphExec_t exec[2];
     hipEvent_t ev, t0, t1;
-    hipStream_t side;                  // second stream: the low sets' kernels
-    hipEvent_t efork, ejoin;
     int64_t nodes;
 };
 
@@ -1434,46 +1443,100 @@ lb_status batch_build(lb_batch *B) {
         if (st == LB_OK) st = upload_list(up, K.d_proj, B->stream);
         if (st != LB_OK) return st;
     }
+    // merged launches: each set group takes its slot in the first registered
+    // kernel pair that has one for it; a kind's projection goes to a merged
+    // launch when its set pair is one of the projection slots, else to a
+    // launch of its own
+    B->plans.clear();
+    for (auto &K : B->kinds) K.merged = false;
+    std::vector<char> placed(B->groups.size(), 0);
+    for (int m = 0; m < B->reg.nmulti; ++m) {
+        const lbk::MultiSet &ms = B->reg.multi[m];
+        const int sn[3] = {6, 4, 3}, se[3] = {ms.eq6, ms.eq4, 2};
+        lb_batch::Plan P{&ms, {-1, -1, -1}, {-1, -1, -1}};
+        bool any = false;
+        for (int s = 0; s < 3; ++s)
+            for (size_t g = 0; g < B->groups.size(); ++g)
+                if (!placed[g] && B->groups[g].n == sn[s] && B->groups[g].eq == se[s]) {
+                    placed[g] = 1;
+                    if (B->groups[g].chunk) {
+                        P.group[s] = int(g);
+                        any = true;
+                    }
+                }
+        for (size_t k = 0; k < B->kinds.size(); ++k) {
+            auto &K = B->kinds[k];
+            if (K.nup + K.ndown == 0 || K.merged) continue;
+            const int nl = K.ks[0]->nS, el = K.ks[0]->eqS, nh = K.ks[1]->nS, eh = K.ks[1]->eqS;
+            int s = -1;
+            if (nl == 3 && el == 2 && nh == 6 && eh == ms.eq6) s = 0;
+            else if (nl == 4 && el == ms.eq4 && nh == 6 && eh == ms.eq6) s = 1;
+            else if (nl == 3 && el == 2 && nh == 4 && eh == ms.eq4) s = 2;
+            if (s < 0) continue;
+            P.kind[s] = int(k);
+            K.merged = true;
+            any = true;
+        }
+        if (any) B->plans.push_back(P);
+    }
+    for (size_t g = 0; g < B->groups.size(); ++g)
+        if (!placed[g])
+            return fail(LB_EUNSUPPORTED, "no batched update kernel for D2Q%d of order %d in this storage",
+                        B->groups[g].n * B->groups[g].n, B->groups[g].eq);
     HIPCHK(hipStreamSynchronize(B->stream));
     for (size_t l = 0; l < B->lat.size(); ++l) B->gen[l] = B->lat[l]->gen;
     return LB_OK;
 }
 
-// the launches of one step of every lattice (source copy cur): one update
-// launch per velocity set (all lattices, both roles), alternating between
-// the batch stream and the side stream; then one projection launch per set
-// pair, alternating likewise; the finish pass after both streams join
-lb_status batch_fork(lb_batch *B) {
-    HIPCHK(hipEventRecord(B->efork, B->stream));
-    HIPCHK(hipStreamWaitEvent(B->side, B->efork, 0));
-    return LB_OK;
-}
-
-lb_status batch_joinside(lb_batch *B) {
-    HIPCHK(hipEventRecord(B->ejoin, B->side));
-    HIPCHK(hipStreamWaitEvent(B->stream, B->ejoin, 0));
-    return LB_OK;
-}
-
+// the launches of one step of every lattice (source copy cur), in stream
+// order: the merged update launches, then the merged projection launches
+// (and those of set pairs outside their slots), then the finish passes
 lb_status batch_launch(lb_batch *B, int cur, uint32_t seed) {
-    lb_status st = batch_fork(B);
-    if (st != LB_OK) return st;
-    for (size_t g = 0; g < B->groups.size(); ++g) {
-        auto &G = B->groups[g];
-        if (!G.chunk) continue;
-        BatchArgs a{B->d_desc[0], G.d_items, G.nitems, G.chunk, cur, 0, seed};
-        G.ks->update_batch(a, 8 * G.chunk, g & 1 ? B->side : B->stream);
+    for (auto &P : B->plans) {
+        BatchMulti m{};
+        m.desc = B->d_desc[0];
+        m.cur = cur;
+        m.seed = seed;
+        int nb = 0;
+        for (int s = 0; s < 3; ++s) {
+            m.start[s] = nb;
+            if (P.group[s] < 0) continue;
+            const auto &G = B->groups[P.group[s]];
+            m.items[s] = G.d_items;
+            m.nitems[s] = G.nitems;
+            m.nsplit[s] = G.chunk;
+            // D2Q36 / D2Q16: a block per item; D2Q9: three items per block
+            nb += 8 * (s < 2 ? G.chunk : (G.chunk + 2) / 3);
+        }
+        m.start[3] = nb;
+        if (nb) P.ms->update(m, nb, B->stream);
     }
-    if ((st = batch_joinside(B)) != LB_OK || (st = batch_fork(B)) != LB_OK) return st;
-    for (size_t k = 0; k < B->kinds.size(); ++k) {
-        auto &K = B->kinds[k];
-        if (!(K.nup + K.ndown)) continue;
-        // one thread per (node, target column)
+    for (auto &P : B->plans) {
+        BatchMulti m{};
+        m.desc = B->d_desc[0];
+        m.cur = cur;
+        m.seed = seed;
+        int nb = 0;
+        for (int s = 0; s < 3; ++s) {
+            m.start[s] = nb;
+            if (P.kind[s] < 0) continue;
+            const auto &K = B->kinds[P.kind[s]];
+            m.items[s] = K.d_proj;
+            m.nitems[s] = K.nup;
+            m.nsplit[s] = K.ndown;
+            // one thread per (node, target column)
+            const int64_t nt = int64_t(K.nup) * K.ks[1]->nS + int64_t(K.ndown) * K.ks[0]->nS;
+            nb += int((nt + 127) / 128);
+        }
+        m.start[3] = nb;
+        if (nb) P.ms->project(m, nb, B->stream);
+    }
+    for (auto &K : B->kinds) {
+        if (K.merged || !(K.nup + K.ndown)) continue;
         const int64_t nt = int64_t(K.nup) * K.ks[1]->nS + int64_t(K.ndown) * K.ks[0]->nS;
         BatchArgs a{B->d_desc[0], K.d_proj, K.nup, 0, cur, K.ndown, seed};
-        K.ks[0]->project_batch(a, int((nt + 127) / 128), k & 1 ? B->side : B->stream);
+        K.ks[0]->project_batch(a, int((nt + 127) / 128), B->stream);
     }
-    if ((st = batch_joinside(B)) != LB_OK) return st;
     for (auto &K : B->kinds) {
         if (!K.nfin) continue;
         BatchArgs a{B->d_desc[0], K.d_fin, K.nfin, 0, cur, 0, seed};
@@ -1580,9 +1643,10 @@ lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stre
     B->exec[0] = B->exec[1] = nullptr;
     B->d_desc[0] = B->d_desc[1] = nullptr;
     B->ev = B->t0 = B->t1 = nullptr;
-    B->side = nullptr;
-    B->efork = B->ejoin = nullptr;
     B->nodes = 0;
+    B->reg = lattices[0]->p.storage == LB_STORE_F64   ? lbk::registry_f64()
+             : lattices[0]->p.storage == LB_STORE_F32 ? lbk::registry_f32()
+                                                       : lbk::registry_bf16();
     auto bail = [&](lb_status st) {
         lb_batch_destroy(B);
         return st;
@@ -1616,7 +1680,6 @@ lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stre
             while (g < B->groups.size() && !(B->groups[g].n == L->ks[s]->nS && B->groups[g].eq == L->ks[s]->eqS)) ++g;
             if (g == B->groups.size()) {
                 lb_batch::SetGroup G;
-                G.ks = L->ks[s];
                 G.n = L->ks[s]->nS;
                 G.eq = L->ks[s]->eqS;
                 B->groups.push_back(G);
@@ -1629,11 +1692,8 @@ lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stre
         if (hipMemcpy(B->d_desc[s], desc[s].data(), sizeof(StepArgs) * n, hipMemcpyHostToDevice) != hipSuccess)
             return bail(fail(LB_EDEVICE, "descriptor upload failed"));
     if (hipEventCreateWithFlags(&B->ev, hipEventDisableTiming) != hipSuccess || hipEventCreate(&B->t0) != hipSuccess ||
-        hipEventCreate(&B->t1) != hipSuccess || hipEventCreateWithFlags(&B->efork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&B->ejoin, hipEventDisableTiming) != hipSuccess)
+        hipEventCreate(&B->t1) != hipSuccess)
         return bail(fail(LB_EDEVICE, "event creation failed"));
-    if (hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking) != hipSuccess)
-        return bail(fail(LB_EDEVICE, "stream creation failed"));
     lb_status st = batch_build(B);
     if (st != LB_OK) return bail(st);
     *out = B;
@@ -1652,12 +1712,6 @@ void lb_batch_destroy(lb_batch *B) {
     for (auto &G : B->groups)
         if (G.d_items) (void)hipFree(G.d_items);
     if (B->d_desc[0]) (void)hipFree(B->d_desc[0]);
-    if (B->side) {
-        (void)hipStreamSynchronize(B->side);
-        (void)hipStreamDestroy(B->side);
-    }
-    if (B->efork) (void)hipEventDestroy(B->efork);
-    if (B->ejoin) (void)hipEventDestroy(B->ejoin);
     if (B->ev) (void)hipEventDestroy(B->ev);
     if (B->t0) (void)hipEventDestroy(B->t0);
     if (B->t1) (void)hipEventDestroy(B->t1);
@@ -1742,8 +1796,15 @@ lb_status lb_batch_autotune(lb_batch *B, int32_t steps, int32_t rows_out[2]) {
 lb_status lb_batch_info(const lb_batch *B, int64_t *nodes, int32_t *launches_per_step, int32_t *kinds) {
     if (!B) return fail(LB_EINVAL, "null batch");
     int nl = 0;
-    for (auto &G : B->groups) nl += G.chunk > 0;
-    for (auto &K : B->kinds) nl += (K.nup + K.ndown > 0) + (K.nfin > 0);
+    for (auto &P : B->plans) {
+        bool up = false, pr = false;
+        for (int s = 0; s < 3; ++s) {
+            up = up || P.group[s] >= 0;
+            pr = pr || P.kind[s] >= 0;
+        }
+        nl += up + pr;
+    }
+    for (auto &K : B->kinds) nl += (!K.merged && K.nup + K.ndown > 0) + (K.nfin > 0);
     if (nodes) *nodes = B->nodes;
     if (launches_per_step) *launches_per_step = nl;
     if (kinds) *kinds = int32_t(B->kinds.size());
