@@ -207,8 +207,10 @@ lb_status lb_get_work_shape(const lb_lattice *L, int32_t rows[2], int32_t order[
 /* Project-written autotuner: for each set, time the update kernel (kernel
  * events over `steps` steps) for each candidate strip height and item order
  * (per-XCD column slabs walked row-major, or column-major) and keep the
- * fastest; the lattice state is saved before and restored after, so the
- * physics is not advanced.  rows_out (may be NULL) receives the choice. */
+ * fastest; with two sets, then time the whole step for the strip heights
+ * within one row of those choices (twice each) and keep the fastest.  The
+ * lattice state is saved before and restored after, so the physics is not
+ * advanced.  rows_out (may be NULL) receives the choice. */
 lb_status lb_autotune(lb_lattice *L, int32_t steps, int32_t rows_out[2]);
 
 /* Number of nodes in each region: [0] low set, [1] high set, [2] interface

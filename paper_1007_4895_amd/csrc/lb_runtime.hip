@@ -958,6 +958,42 @@ lb_status lb_autotune(lb_lattice *L, int32_t steps, int32_t rows_out[2]) {
     L->tuning = false;
     L->ev_used = 0;
     L->ev_kind.clear();
+    // then the whole step as it runs (both sets' updates merged or in turn,
+    // the projection): strips next to the per-set choices, each timed twice
+    // over `steps` steps, the faster time counting
+    if (L->count[0] && L->count[1]) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const int p0 = L->strip[0], p1 = L->strip[1];
+        double best = 1e300;
+        int b0 = p0, b1 = p1;
+        for (int a = std::max(1, p0 - 1); a <= p0 + 1 && st == LB_OK; ++a)
+            for (int b = std::max(1, p1 - 1); b <= p1 + 1 && st == LB_OK; ++b) {
+                L->strip[0] = a;
+                L->strip[1] = b;
+                if ((st = upload_regions(L)) != LB_OK) break;
+                for (int rep = 0; rep < 2 && st == LB_OK; ++rep) {
+                    if (hipEventRecord(e0, L->stream) != hipSuccess) st = fail(LB_EDEVICE, "event record failed");
+                    for (int k = 0; k < steps && st == LB_OK; ++k) st = one_step(L);
+                    if (st != LB_OK) break;
+                    float ms = 0;
+                    if (hipEventRecord(e1, L->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                        st = fail(LB_EDEVICE, "event timing failed");
+                    else if (ms < best) {
+                        best = ms;
+                        b0 = a;
+                        b1 = b;
+                    }
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != LB_OK) return st;
+        L->strip[0] = b0;
+        L->strip[1] = b1;
+    }
     if ((st = upload_regions(L)) != LB_OK) return st;
     L->cur = cur0;
     st = lb_set_state(L, saved.data(), saved.size());
