@@ -93,6 +93,38 @@ def test_batch_bit_identical_to_single(lb, storage):
     B.close()
 
 
+# FP64 only: second-order D2Q16 / D2Q36 sets (a second merged update and
+# projection launch) and a pair of equal sets with bands (a projection
+# launch of its own), beside a pair of the first merged launch
+SECOND_ORDER = [
+    (8, 30, (4, 2, 6, 2), (6, 6), dict(gx=2e-5)),
+    (70, 24, (3, 2, 6, 2), (5, 5), dict(u_wall=((-0.03, 0.0), (0.03, 0.0)))),
+    (16, 40, (3, 2, 4, 2), (4, 4), dict(gx=1e-5)),
+    (64, 20, (3, 2, 3, 2), (4, 4), dict(gx=3e-5)),
+    (8, 33, (4, 3, 6, 4), (10, 10), dict(gx=2e-5)),
+]
+
+
+def test_batch_second_order_sets_and_equal_pairs(lb):
+    A = [_make(lb, c, "f64", 300 + k) for k, c in enumerate(SECOND_ORDER)]
+    S = [_make(lb, c, "f64", 300 + k) for k, c in enumerate(SECOND_ORDER)]
+    B = lb.Batch(A)
+    nodes, launches, kinds = B.info()
+    assert kinds == len(SECOND_ORDER)
+    # two merged updates, two merged projections, one projection of its own
+    assert launches == 5, launches
+    B.step(6)
+    for L in S:
+        L.step(6)
+    assert all(_same(a, s) for a, s in zip(A, S))
+    B.set_graph(3)
+    B.step(7)
+    for L in S:
+        L.step(7)
+    assert all(_same(a, s) for a, s in zip(A, S))
+    B.close()
+
+
 def test_batch_region_change_and_parity_guard(lb):
     A = [_make(lb, c, "f64", 200 + k) for k, c in enumerate(MIXED[:4])]
     S = [_make(lb, c, "f64", 200 + k) for k, c in enumerate(MIXED[:4])]
