@@ -271,13 +271,14 @@ lb_status lb_set_closure(lb_lattice *L, const float *params, const float *norm);
 
 /* ---------------------------------------------------------------------
  * Batches: many independent lattices (channels of different size, Kn and
- * velocity-set pair) advanced together.  Each step issues, per velocity-set
- * pair present, one launch per kernel (update of each set, interface
- * projection, finish) covering the work items of every lattice of that
- * pair, instead of one launch per kernel per lattice; with a graph segment
- * set, runs of that many steps are captured once into a HIP graph and
- * replayed.  Every step of every lattice is the same computation as
- * lb_step (bit-identical results).
+ * velocity-set pair) advanced together.  Each step issues, in order on the
+ * batch stream, one update launch covering every velocity set of every
+ * lattice, one interface-projection launch covering the set pairs D2Q9 /
+ * D2Q36, D2Q16 / D2Q36 and D2Q9 / D2Q16 (other pairs: one launch each),
+ * and the finish passes of lattices that need them, instead of launches
+ * per lattice; with a graph segment set, runs of that many steps are
+ * captured once into a HIP graph and replayed.  Every step of every
+ * lattice is the same computation as lb_step (bit-identical results).
  *
  * The lattices stay owned by the caller and must outlive the batch; they
  * must share a storage type, use the Hermite interface, have no learned
