@@ -196,8 +196,23 @@ def main():
         t = json.load(open(TRAFFIC_FILE))
         if t.get("kernel_hash") == kernel_hash():
             traffic = t.get("hbm_bytes_per_launch")
+    # context: a plain device copy of the same bytes (half read, half
+    # written), timed with events like the kernel
+    x = torch.empty(dom_bytes // 8, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(20):
+        y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(200):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * x.numel() * 4 / (e0.elapsed_time(e1) / 200 * 1e-3) / 1e9
+    del x, y
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "copy_same_bytes_gbs": round(copy_gbs, 1),
                 "kernel": "k_update_pair<F32, D2Q9 order 2 + D2Q36 order 4>", "bytes_per_launch": dom_bytes,
                 "avg_launch_ms": round(avg_ms, 5), "launches": n_h, "timing": "hipExtLaunchKernelGGL events"}
     out = {
