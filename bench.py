@@ -61,6 +61,49 @@ def timed(L, steps, torch):
     return time.perf_counter() - t0
 
 
+def large_section(lb, W, torch, steps):
+    """The C2 channel four times wider (4096 x 513): its two copies of the
+    populations (265 MB coupled, 605 MB all-D2Q36) exceed the 256 MB
+    Infinity Cache, so every step streams from HBM; coupled and all-D2Q36,
+    each autotuned, with the dominant kernel timed by events."""
+    c = W.POISEUILLE_C2
+    nx = 4 * c["nx"]
+    nodes = nx * (c["ny"] + 1)
+
+    def mk(all_high):
+        p = lb.make_params(nx, c["ny"], kn=KN_TIMED, n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"],
+                           eq_high=c["eq_high"], gx=c["gx"], storage=c["storage"])
+        L = lb.Lattice(p)
+        L.set_regions(*((c["ny"] + 1, 0) if all_high else c["bands"]))
+        L.init_equilibrium()
+        return L
+
+    out = {"workload": f"poiseuille_c2 widened: {nx}x{c['ny'] + 1}, Kn={KN_TIMED}, D2Q36 (order 4) in 64 rows at "
+                       "each wall, D2Q9 core, FP32", "nodes": nodes}
+    for name, all_high in (("coupled", False), ("all_d2q36", True)):
+        L = mk(all_high)
+        cnt = L.region_counts()
+        alg = 4 * 2 * (9 * cnt[0] + 36 * cnt[1]) if not all_high else 4 * 2 * 36 * nodes
+        L.autotune(50)
+        L.step(100)
+        sec = timed(L, steps, torch)
+        L.set_timing(True)
+        L.step(500)
+        ms_h, n_h, _, _ = L.kernel_times()
+        L.set_timing(False)
+        avg_ms = ms_h / max(n_h, 1)
+        out[name] = {"mlups": round(nodes * steps / sec / 1e6, 1), "us_per_step": round(1e6 * sec / steps, 2),
+                     "hbm_gbs_algorithmic_step": round(alg * steps / sec / 1e9, 1),
+                     "update_kernel_us": round(1e3 * avg_ms, 2),
+                     "update_kernel_gbs": round(alg / (avg_ms * 1e-3) / 1e9, 1),
+                     "update_kernel_frac": round(alg / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "work_shape": ",".join(str(v) for v in (*L.work_shape()[0], *L.work_shape()[1]))}
+        del L
+    out["speedup_vs_all_d2q36"] = round(out["coupled"]["mlups"] / out["all_d2q36"]["mlups"], 3)
+    out["timed_steps"] = steps
+    return out
+
+
 def batch_section(lb, W, torch):
     """The 128-channel workload stepped as one batch (graph-captured
     segments, autotuned strips) against stepping each channel with its own
@@ -125,6 +168,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the strip autotuner")
     ap.add_argument("--no-batch", action="store_true", help="skip the 128-channel batch section")
     ap.add_argument("--batch-only", action="store_true", help="run only the 128-channel batch section (profiling)")
+    ap.add_argument("--no-large", action="store_true", help="skip the 4096-column (beyond the Infinity Cache) section")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="steps of the kernel-timing pass (the dominant kernel's roofline)")
     ap.add_argument("--shape", type=str, default="",
@@ -286,6 +330,11 @@ def main():
     out["gate_1e-3"] = gated
     b0 = str(c["bands"][0])
     out["e_model_at_timed_config"] = emodel.get(str(kn_t), {}).get(b0)
+
+    # ------------- the same channel 4x wider: working set beyond the Infinity Cache
+    if not args.no_large:
+        out["c2_wide_4096"] = large_section(lb, W, torch, 2000)
+        print(f"wide: {out['c2_wide_4096']}", flush=True)
 
     # ------------------- 128 independent channels: one batch vs one launch per case
     if not args.no_batch:
