@@ -31,10 +31,10 @@ struct Inst {
     static void update_pair(const StepArgs &l, const StepArgs &h, int nb_h, int nb_l, hipStream_t s, hipEvent_t e0,
                             hipEvent_t e1) {
         if (e0)
-            hipExtLaunchKernelGGL((k_update_pair<ST, S, O>), dim3(nb_h + nb_l), dim3(64 * update_split<O>()), 0, s, e0,
+            hipExtLaunchKernelGGL((k_update_pair<ST, S, O>), dim3(nb_h + nb_l), dim3(64 * pair_split<O>()), 0, s, e0,
                                   e1, 0, l, h, nb_h);
         else
-            hipLaunchKernelGGL((k_update_pair<ST, S, O>), dim3(nb_h + nb_l), dim3(64 * update_split<O>()), 0, s, l, h,
+            hipLaunchKernelGGL((k_update_pair<ST, S, O>), dim3(nb_h + nb_l), dim3(64 * pair_split<O>()), 0, s, l, h,
                                nb_h);
     }
     static void finish_batch(const BatchArgs &a, int grid, hipStream_t s) {
@@ -94,7 +94,7 @@ struct Inst {
         k.closure_infer = &closure_infer;
         k.closure_samples = &closure_samples;
         k.update_pair = update_split<S>() == 1 ? &update_pair : nullptr;
-        k.pair_split = update_split<O>();
+        k.pair_split = pair_split<O>();
         k.finish_batch = &finish_batch;
         k.project_batch = &project_batch;
         k.update_kernel = reinterpret_cast<const void *>(&k_update<ST, S, O>);
@@ -105,12 +105,13 @@ struct Inst {
 template <class ST, int E6, int E4>
 struct MultiInst {
     static void update(const BatchMulti &m, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((k_update_multi<ST, lbt::VSet<6, E6>, lbt::VSet<4, E4>>), dim3(grid), dim3(192), 0, s, m);
+        hipLaunchKernelGGL((k_update_multi<ST, lbt::VSet<6, E6>, lbt::VSet<4, E4>>), dim3(grid),
+                           dim3(64 * multi_waves()), 0, s, m);
     }
     static void project(const BatchMulti &m, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_project_multi<ST, lbt::VSet<6, E6>, lbt::VSet<4, E4>>), dim3(grid), dim3(128), 0, s, m);
     }
-    static MultiSet make() { return MultiSet{E6, E4, &update, &project}; }
+    static MultiSet make() { return MultiSet{E6, E4, multi_waves(), &update, &project}; }
 };
 
 }  // namespace lbk

@@ -40,6 +40,10 @@
 #ifndef LB_WAVES36_PAIR
 #define LB_WAVES36_PAIR 4
 #endif
+// waves per D2Q36 item in the merged launch with D2Q9 (measured best: 2)
+#ifndef LB_PAIR_SPLIT36
+#define LB_PAIR_SPLIT36 2
+#endif
 
 namespace lbk {
 
@@ -475,15 +479,20 @@ __device__ void finish_node(const Buf &self, const Buf &other, int copy, int i, 
 // large quantities cancel in FP32.
 template <class SS>
 constexpr int update_split() { return SS::Q == 36 ? LB_SPLIT36 : SS::Q == 16 ? 2 : 1; }
+// the same for the high set of the merged launch with D2Q9 (k_update_pair)
+template <class SS>
+constexpr int pair_split() { return SS::Q == 36 ? LB_PAIR_SPLIT36 : update_split<SS>(); }
 
-template <class T, int SPLIT>
-__device__ __forceinline__ T (*lds_moments())[3][SPLIT][64] {
-    __shared__ T sm[2][3][SPLIT][64];
+// LDS of a split update: per y-abscissa partial moments (double-buffered
+// by row) and wall fluxes; one allocation per set and split
+template <class T, int N, int SPLIT>
+__device__ __forceinline__ T (*lds_moments())[2][N][64] {
+    __shared__ T sm[2][2][N][64];
     return sm;
 }
-template <class T, int SPLIT>
-__device__ __forceinline__ T (*lds_wall())[SPLIT][64] {
-    __shared__ T sn[2][SPLIT][64];
+template <class T, int N, int SPLIT>
+__device__ __forceinline__ T (*lds_wall())[N][64] {
+    __shared__ T sn[2][N][64];
     return sn;
 }
 
@@ -494,33 +503,34 @@ constexpr int update_waves() { return SS::Q == 36 ? LB_WAVES36 : SS::Q == 16 ? 4
 template <class SS>
 constexpr int pair_waves() { return SS::Q == 36 ? LB_WAVES36_PAIR : update_waves<SS>(); }
 
-template <class ST, class SS, class OO, int WV, bool NW = false>
+template <class ST, class SS, class OO, int WV, bool NW = false, int SPL = update_split<SS>()>
 __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
                                             const int j0, const int j1, const int lane, const int S = 0);
 
 // one work item of one lattice: 64 columns x rows j0..j1, or (NW, a
 // narrow lattice) 64 / (nx + 4) lane groups of nx + 4 columns each, group
-// g marching rows j0 + g S .. j0 + (g + 1) S (clipped to j1)
-template <class ST, class SS, class OO, bool NW = false>
+// g marching rows j0 + g S .. j0 + (g + 1) S (clipped to j1); SPL waves
+// share the populations (the result does not depend on SPL)
+template <class ST, class SS, class OO, bool NW = false, int SPL = update_split<SS>()>
 __device__ __forceinline__ void update_item(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
                                             const int j0, const int j1, const int S = 0) {
-    constexpr int SPLIT = update_split<SS>();
+    constexpr int SPLIT = SPL;
     const int lane = threadIdx.x & 63;
     // the wave index is wave-uniform: each wave runs the row loop compiled
     // for its own abscissae, so every population's upwind direction and
     // constants are known at compile time
     const int wv = SPLIT > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6) : 0;
-    if (wv == 0) update_rows<ST, SS, OO, 0, NW>(A, cur, seed, i0, j0, j1, lane, S);
+    if (wv == 0) update_rows<ST, SS, OO, 0, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
     if constexpr (SPLIT > 1) {
-        if (wv == 1) update_rows<ST, SS, OO, 1, NW>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 1) update_rows<ST, SS, OO, 1, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
     }
     if constexpr (SPLIT > 2) {
-        if (wv == 2) update_rows<ST, SS, OO, 2, NW>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 2) update_rows<ST, SS, OO, 2, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
     }
     if constexpr (SPLIT > 3) {
-        if (wv == 3) update_rows<ST, SS, OO, 3, NW>(A, cur, seed, i0, j0, j1, lane, S);
-        if (wv == 4) update_rows<ST, SS, OO, 4, NW>(A, cur, seed, i0, j0, j1, lane, S);
-        if (wv == 5) update_rows<ST, SS, OO, 5, NW>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 3) update_rows<ST, SS, OO, 3, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 4) update_rows<ST, SS, OO, 4, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 5) update_rows<ST, SS, OO, 5, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
     }
 }
 
@@ -545,18 +555,18 @@ void k_update(const StepArgs A) {
 // their waves share the machine instead of running back to back.
 
 template <class ST, class LS, class HS>
-__global__ __launch_bounds__(64 * update_split<HS>())
+__global__ __launch_bounds__(64 * pair_split<HS>())
 __attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : pair_waves<HS>())))
 void k_update_pair(const StepArgs L, const StepArgs H, const int nb_h) {
     if constexpr (update_split<LS>() == 1) {
-        constexpr int SPLIT = update_split<HS>();
+        constexpr int SPLIT = pair_split<HS>();
         const int b = blockIdx.x;
         if (b < nb_h) {
             const int it = (b & 7) * H.chunk + (b >> 3);
             if (it >= H.nitems) return;
             const int i0 = H.items[4 * it], j0 = H.items[4 * it + 1], j1 = H.items[4 * it + 2];
             if (j0 >= j1) return;
-            update_item<ST, HS, LS>(H, H.cur, H.seed, i0, j0, j1);
+            update_item<ST, HS, LS, false, SPLIT>(H, H.cur, H.seed, i0, j0, j1);
         } else {
             // low items: XCD slab (b' mod 8) of L.chunk items, SPLIT per block
             const int bl = b - nb_h;
@@ -575,10 +585,10 @@ void k_update_pair(const StepArgs L, const StepArgs H, const int nb_h) {
 // The update of a batch of independent lattices, every velocity set in one
 // launch.  Item (i0, j0, j1, l) belongs to lattice (and side) l, whose
 // arguments are M.desc[l]; the lattices of a batch step together, so the
-// copy parity is the launch's.  Blocks have three waves: a D2Q36 item takes
-// a whole block, a D2Q16 item two of its waves (the third leaves at once: a
-// barrier waits only for the waves still running), and a D2Q9 item a single
-// wave, three to a block (S36 and S16 are the D2Q36 and D2Q16 sets of the
+// copy parity is the launch's.  Blocks have multi_waves() waves: a D2Q36
+// or D2Q16 item takes as many as its split (waves left over leave at once:
+// a barrier waits only for the waves still running), and a D2Q9 item a
+// single wave, multi_waves() to a block (S36 and S16 are the D2Q36 and D2Q16 sets of the
 // batch, of their equilibrium orders).  Within each slot the blocks are
 // mapped to items XCD by XCD as in the single-lattice kernels (slot starts
 // are multiples of 8).
@@ -602,23 +612,27 @@ __device__ __forceinline__ void batch_item(const BatchMulti &M, const int slot, 
     else update_item<ST, SS, SS>(A, M.cur, M.seed, i0, j0, j1);
 }
 
+// waves per block of the batch update: enough for a D2Q36 or a D2Q16 item
+constexpr int multi_waves() { return LB_SPLIT36 > 2 ? LB_SPLIT36 : 2; }
+
 template <class ST, class S36, class S16>
-__global__ __launch_bounds__(192)
+__global__ __launch_bounds__(64 * multi_waves())
 __attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : LB_WAVES36_PAIR)))
 void k_update_multi(const BatchMulti M) {
     using S9 = lbt::VSet<3, 2>;
-    static_assert(update_split<S36>() == 3 && update_split<S16>() == 2 && update_split<S9>() == 1,
-                  "three-wave blocks");
+    constexpr int MW = multi_waves();
+    static_assert(update_split<S36>() <= MW && update_split<S16>() <= MW && update_split<S9>() == 1,
+                  "an item's waves fit a block");
     const int b = blockIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
     if (b < M.start[1]) {
-        batch_item<ST, S36>(M, 0, (b & 7) * M.nsplit[0] + (b >> 3));
+        if (w < update_split<S36>()) batch_item<ST, S36>(M, 0, (b & 7) * M.nsplit[0] + (b >> 3));
     } else if (b < M.start[2]) {
         const int bl = b - M.start[1];
-        if (w < 2) batch_item<ST, S16>(M, 1, (bl & 7) * M.nsplit[1] + (bl >> 3));
+        if (w < update_split<S16>()) batch_item<ST, S16>(M, 1, (bl & 7) * M.nsplit[1] + (bl >> 3));
     } else {
         const int bl = b - M.start[2];
-        const int pos = 3 * (bl >> 3) + w;
+        const int pos = MW * (bl >> 3) + w;
         if (pos < M.nsplit[2]) batch_item<ST, S9>(M, 2, (bl & 7) * M.nsplit[2] + pos);
     }
 }
@@ -638,14 +652,19 @@ void k_update_multi(const BatchMulti M) {
         }                                                                                \
     }
 
-template <class ST, class SS, class OO, int WV, bool NW>
+template <class ST, class SS, class OO, int WV, bool NW, int SPL>
 __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
                                             const int j0, const int j1, const int lane, const int S) {
+    // multiply-adds are fused within an expression only (not across
+    // statements, where the choice would depend on the surrounding code):
+    // every instantiation (split, narrow or wide, merged or alone) then
+    // rounds a population's update the same way
+#pragma clang fp contract(on)
     using T = typename ST::M;
     using SV = typename ST::S;
     using TB = typename SS::T;
     constexpr int N = SS::N, Q = SS::Q, EQ = SS::EQ;
-    constexpr int SPLIT = update_split<SS>();
+    constexpr int SPLIT = SPL;
     constexpr int NQ = N / SPLIT;      // y-abscissae per wave
     constexpr int QW = NQ * N;         // populations per wave
     constexpr int q0 = WV * NQ;
@@ -764,10 +783,10 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     const T om_rho = T(A.ph.omega0 / A.ph.rho_ref);
     const T dtT = T(A.ph.dt), gxT = T(A.ph.gx), gyT = T(A.ph.gy);
 
-    // LDS: partial moments (double-buffered by row) and wall fluxes; one
-    // allocation per kernel, shared by the wave variants
-    T (*sm)[3][SPLIT][64] = lds_moments<T, SPLIT>();
-    T (*sn)[SPLIT][64] = lds_wall<T, SPLIT>();
+    // LDS: per-abscissa partial moments (double-buffered by row) and wall
+    // fluxes, shared by the wave variants
+    T (*sm)[2][N][64] = lds_moments<T, N, SPLIT>();
+    T (*sn)[N][64] = lds_wall<T, N, SPLIT>();
 
     // (narrow: the loop counts a group's rows, S for every group)
     for (int jr = NW ? 0 : j0; jr < (NW ? S : j1); ++jr) {
@@ -786,10 +805,15 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
         const unsigned vw = NW ? (wall_l ? vs : OOB) : vs;
         const bool bottom = j == 0;
         const int gj1 = bottom ? -1 : g.ny + 1, gj2 = bottom ? -2 : g.ny + 2;
+        // flux of the stored values into the wall: per y-abscissa partial
+        // sums (nq), summed over the abscissae in order like the moments
         T nacc = T(0);
 
-        // moments of the centre values: rho' = sum f (shifted), j = sum xi f
-        T rp = T(0), jx = T(0), jy = T(0);
+        // moments of the centre values: rho' = sum f (shifted), j = sum xi f.
+        // Per y-abscissa partial sums, then summed over the abscissae in
+        // order (through LDS when the populations are split over waves), so
+        // the moments do not depend on the split.
+        T sqv[NQ], sxv[NQ];
 #pragma unroll
         for (int qq = 0; qq < NQ; ++qq) {
             T sq = T(0), sxq = T(0);
@@ -798,24 +822,31 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 sq += c[p + N * qq];
                 sxq += T(TB::rule.x[p]) * c[p + N * qq];
             }
-            rp += sq;
-            jx += sxq;
-            jy += T(TB::rule.x[q0 + qq]) * sq;
+            sqv[qq] = sq;
+            sxv[qq] = sxq;
         }
-        if constexpr (SPLIT > 1) {
-            const int buf = NW ? jr & 1 : (j - j0) & 1;
-            sm[buf][0][wv][lane] = rp;
-            sm[buf][1][wv][lane] = jx;
-            sm[buf][2][wv][lane] = jy;
-            __syncthreads();
-            rp = sm[buf][0][0][lane];
-            jx = sm[buf][1][0][lane];
-            jy = sm[buf][2][0][lane];
+        T rp = T(0), jx = T(0), jy = T(0);
+        if constexpr (SPLIT == 1) {
 #pragma unroll
-            for (int w = 1; w < SPLIT; ++w) {
-                rp += sm[buf][0][w][lane];
-                jx += sm[buf][1][w][lane];
-                jy += sm[buf][2][w][lane];
+            for (int q = 0; q < N; ++q) {
+                rp += sqv[q];
+                jx += sxv[q];
+                jy += T(TB::rule.x[q]) * sqv[q];
+            }
+        } else {
+            const int buf = NW ? jr & 1 : (j - j0) & 1;
+#pragma unroll
+            for (int qq = 0; qq < NQ; ++qq) {
+                sm[buf][0][q0 + qq][lane] = sqv[qq];
+                sm[buf][1][q0 + qq][lane] = sxv[qq];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                const T sq = sm[buf][0][q][lane];
+                rp += sq;
+                jx += sm[buf][1][q][lane];
+                jy += T(TB::rule.x[q]) * sq;
             }
         }
         const T rho = rho_shift + rp;
@@ -859,6 +890,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 B[k] = s;
             }
             const double xq = TB::rule.x[q];
+            T nq = T(0);
 #pragma unroll
             for (int p = 0; p < N; ++p) {
                 const int k = p + N * qq;
@@ -919,7 +951,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                     // xi_y = 0 are final: copy them to the ghost rows
                     const bool leaving = bottom ? (xq > 0.0) : (xq < 0.0);
                     if (!leaving) {
-                        if (xq != 0.0) nacc += T(lbt::cabs(xq)) * acc;
+                        if (xq != 0.0) nq += T(lbt::cabs(xq)) * acc;
                         LB_ST(LB_VO(vw, gj1), LB_SO(a, gj1), acc)
                         LB_ST(LB_VO(vw, gj2), LB_SO(a, gj2), acc)
                     }
@@ -928,15 +960,17 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 // neighbour arithmetic to the top of the row (register blow-up)
                 __builtin_amdgcn_sched_barrier(0);
             }
+            if (wall) {
+                if constexpr (SPLIT > 1) sn[bottom ? 0 : 1][q][lane] = nq;
+                else nacc += nq;
+            }
         }
         if (wall) {
             const int ws = bottom ? 0 : 1;
             if constexpr (SPLIT > 1) {
-                sn[ws][wv][lane] = nacc;
                 __syncthreads();
-                nacc = sn[ws][0][lane];
 #pragma unroll
-                for (int w = 1; w < SPLIT; ++w) nacc += sn[ws][w][lane];
+                for (int q = 0; q < N; ++q) nacc += sn[ws][q][lane];
             }
             T Kw, Dw;
             if constexpr (sizeof(T) == 8) {

@@ -45,6 +45,7 @@ struct KernelSet {
 using MultiFn = void (*)(const lbi::BatchMulti &, int grid, hipStream_t);
 struct MultiSet {
     int eq6, eq4;
+    int waves;   // waves per block of the update (D2Q9 items per block)
     MultiFn update, project;
 };
 

@@ -1541,8 +1541,9 @@ lb_status batch_launch(lb_batch *B, int cur, uint32_t seed) {
             m.items[s] = G.d_items;
             m.nitems[s] = G.nitems;
             m.nsplit[s] = G.chunk;
-            // D2Q36 / D2Q16: a block per item; D2Q9: three items per block
-            nb += 8 * (s < 2 ? G.chunk : (G.chunk + 2) / 3);
+            // D2Q36 / D2Q16: a block per item; D2Q9: one item per wave
+            const int W = P.ms->waves;
+            nb += 8 * (s < 2 ? G.chunk : (G.chunk + W - 1) / W);
         }
         m.start[3] = nb;
         if (nb) P.ms->update(m, nb, B->stream);
