@@ -44,6 +44,17 @@
 #ifndef LB_PAIR_SPLIT36
 #define LB_PAIR_SPLIT36 2
 #endif
+// the batch update of every set in one launch: waves per D2Q36 and D2Q16
+// item, and the occupancy it is compiled for
+#ifndef LB_MULTI_SPLIT36
+#define LB_MULTI_SPLIT36 3
+#endif
+#ifndef LB_MULTI_SPLIT16
+#define LB_MULTI_SPLIT16 2
+#endif
+#ifndef LB_MULTI_WAVES
+#define LB_MULTI_WAVES LB_WAVES36_PAIR
+#endif
 
 namespace lbk {
 
@@ -482,6 +493,9 @@ constexpr int update_split() { return SS::Q == 36 ? LB_SPLIT36 : SS::Q == 16 ? 2
 // the same for the high set of the merged launch with D2Q9 (k_update_pair)
 template <class SS>
 constexpr int pair_split() { return SS::Q == 36 ? LB_PAIR_SPLIT36 : update_split<SS>(); }
+// ... and in the batch update
+template <class SS>
+constexpr int multi_split() { return SS::Q == 36 ? LB_MULTI_SPLIT36 : SS::Q == 16 ? LB_MULTI_SPLIT16 : 1; }
 
 // LDS of a split update: per y-abscissa partial moments (double-buffered
 // by row) and wall fluxes; one allocation per set and split
@@ -608,28 +622,28 @@ __device__ __forceinline__ void batch_item(const BatchMulti &M, const int slot, 
     const StepArgs &A = *(const StepArgs *)((const __attribute__((address_space(4))) StepArgs *)M.desc + l);
     // a negative first column marks a narrow lattice's item: -i0 rows per
     // lane group
-    if (i0 < 0) update_item<ST, SS, SS, true>(A, M.cur, M.seed, 0, j0, j1, -i0);
-    else update_item<ST, SS, SS>(A, M.cur, M.seed, i0, j0, j1);
+    if (i0 < 0) update_item<ST, SS, SS, true, multi_split<SS>()>(A, M.cur, M.seed, 0, j0, j1, -i0);
+    else update_item<ST, SS, SS, false, multi_split<SS>()>(A, M.cur, M.seed, i0, j0, j1);
 }
 
 // waves per block of the batch update: enough for a D2Q36 or a D2Q16 item
-constexpr int multi_waves() { return LB_SPLIT36 > 2 ? LB_SPLIT36 : 2; }
+constexpr int multi_waves() { return LB_MULTI_SPLIT36 > LB_MULTI_SPLIT16 ? LB_MULTI_SPLIT36 : LB_MULTI_SPLIT16; }
 
 template <class ST, class S36, class S16>
 __global__ __launch_bounds__(64 * multi_waves())
-__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : LB_WAVES36_PAIR)))
+__attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : LB_MULTI_WAVES)))
 void k_update_multi(const BatchMulti M) {
     using S9 = lbt::VSet<3, 2>;
     constexpr int MW = multi_waves();
-    static_assert(update_split<S36>() <= MW && update_split<S16>() <= MW && update_split<S9>() == 1,
+    static_assert(multi_split<S36>() <= MW && multi_split<S16>() <= MW && multi_split<S9>() == 1,
                   "an item's waves fit a block");
     const int b = blockIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
     if (b < M.start[1]) {
-        if (w < update_split<S36>()) batch_item<ST, S36>(M, 0, (b & 7) * M.nsplit[0] + (b >> 3));
+        if (w < multi_split<S36>()) batch_item<ST, S36>(M, 0, (b & 7) * M.nsplit[0] + (b >> 3));
     } else if (b < M.start[2]) {
         const int bl = b - M.start[1];
-        if (w < update_split<S16>()) batch_item<ST, S16>(M, 1, (bl & 7) * M.nsplit[1] + (bl >> 3));
+        if (w < multi_split<S16>()) batch_item<ST, S16>(M, 1, (bl & 7) * M.nsplit[1] + (bl >> 3));
     } else {
         const int bl = b - M.start[2];
         const int pos = MW * (bl >> 3) + w;
