@@ -919,19 +919,20 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 // ((1 - om) f would move it by eps/om relative)
                 T acc = f - om * f + Sa;
 
-                // x fluxes: neighbours from the adjacent lanes
+                // x fluxes: neighbours from the adjacent lanes.  The limited
+                // slope of column i, L_i = minmod(f_i - f_{i-1}, f_{i+1} - f_i),
+                // is the one both faces need: the upwind face of column i
+                // takes L_i and its neighbour's from the adjacent lane
+                // (the same values as forming each face's slope in place)
                 if (xp != 0.0) {
                     const T fm1 = nbr<DPP_WAVE_SHR1>(f);
                     const T fp1 = nbr<DPP_WAVE_SHL1>(f);
                     const T dm = f - fm1, dp = fp1 - f;
+                    const T L = minmod(dm, dp);
                     if (xp > 0.0) {
-                        const T dmm = nbr<DPP_WAVE_SHR1>(dm);
-                        const T Lp = minmod(dm, dp), Lm = minmod(dmm, dm);
-                        acc = acc - nu[p] * dm - kk[p] * (Lp - Lm);
+                        acc = acc - nu[p] * dm - kk[p] * (L - nbr<DPP_WAVE_SHR1>(L));
                     } else {
-                        const T dpp_ = nbr<DPP_WAVE_SHL1>(dp);
-                        const T Lp = minmod(dpp_, dp), Lm = minmod(dp, dm);
-                        acc = acc - nu[p] * dp - kk[p] * (Lp - Lm);
+                        acc = acc - nu[p] * dp - kk[p] * (nbr<DPP_WAVE_SHL1>(L) - L);
                     }
                 }
                 // y fluxes (register window)
