@@ -205,7 +205,8 @@ lb_status lb_set_work_shape(lb_lattice *L, const int32_t rows[2], const int32_t 
 lb_status lb_get_work_shape(const lb_lattice *L, int32_t rows[2], int32_t order[2]);
 
 /* Project-written autotuner: for each set, time the update kernel (kernel
- * events over `steps` steps) for each candidate strip height and item order
+ * events over `steps` steps, twice, the faster pass counting) for each
+ * candidate strip height and item order
  * (per-XCD column slabs walked row-major, or column-major) and keep the
  * fastest; with two sets, then time the whole step for the strip heights
  * within one row of those choices (twice each) and keep the fastest.  The

@@ -932,18 +932,23 @@ lb_status lb_autotune(lb_lattice *L, int32_t steps, int32_t rows_out[2]) {
             L->strip[s] = c;
             L->order[s] = ord;
             if ((st = upload_regions(L)) != LB_OK) return st;
-            L->timing = true;
-            L->ev_used = 0;
-            L->ev_kind.clear();
-            for (int k = 0; k < steps; ++k)
-                if ((st = one_step(L)) != LB_OK) return st;
-            HIPCHK(hipStreamSynchronize(L->stream));
-            double t = 0;
-            for (size_t k = 0; k < L->ev_kind.size(); ++k) {
-                if (L->ev_kind[k] != s) continue;
-                float ms = 0;
-                HIPCHK(hipEventElapsedTime(&ms, L->ev_pool[2 * k], L->ev_pool[2 * k + 1]));
-                t += ms;
+            // timed twice, the faster pass counting
+            double t = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                L->timing = true;
+                L->ev_used = 0;
+                L->ev_kind.clear();
+                for (int k = 0; k < steps; ++k)
+                    if ((st = one_step(L)) != LB_OK) return st;
+                HIPCHK(hipStreamSynchronize(L->stream));
+                double tr = 0;
+                for (size_t k = 0; k < L->ev_kind.size(); ++k) {
+                    if (L->ev_kind[k] != s) continue;
+                    float ms = 0;
+                    HIPCHK(hipEventElapsedTime(&ms, L->ev_pool[2 * k], L->ev_pool[2 * k + 1]));
+                    tr += ms;
+                }
+                t = std::min(t, tr);
             }
             if (t < best) {
                 best = t;
