@@ -102,6 +102,10 @@ struct BatchArgs {
 // list, taking the blocks [start[s], start[s + 1]).  Update slots are the
 // sets D2Q36, D2Q16, D2Q9; projection slots the pairs D2Q9/D2Q36,
 // D2Q16/D2Q36, D2Q9/D2Q16.
+// batch item of an 8-column periodic lattice (x neighbours wrapped inside
+// 8-lane groups): its first entry is -(rows per group + NW_WRAP)
+constexpr int32_t NW_WRAP = 0x10000;
+
 struct BatchMulti {
     const StepArgs *desc;       // device: per lattice and side, as for BatchArgs
     const int32_t *items[3];    // device item lists (NULL for an empty slot)

@@ -190,6 +190,31 @@ __device__ __forceinline__ double nbr(double src) {
     return dpp<CTRL>(src, src);
 }
 
+// The value of column col - 1 (xleft) or col + 1 (xright): the adjacent
+// lane, or (WR: 8-column periodic lattice, eight columns per 8-lane group)
+// the adjacent lane in the group with the wrap-around taken from the
+// group's other end, by shifts inside the 16-lane DPP rows.
+template <bool WR, class T>
+__device__ __forceinline__ T xleft(T v, int col) {
+    if constexpr (WR) {
+        const T a = nbr<0x107>(v);   // row_shl:7, lane l <- l + 7
+        const T b = nbr<0x111>(v);   // row_shr:1, lane l <- l - 1
+        return col == 0 ? a : b;
+    } else {
+        return nbr<DPP_WAVE_SHR1>(v);
+    }
+}
+template <bool WR, class T>
+__device__ __forceinline__ T xright(T v, int col) {
+    if constexpr (WR) {
+        const T a = nbr<0x117>(v);   // row_shr:7, lane l <- l - 7
+        const T b = nbr<0x101>(v);   // row_shl:1, lane l <- l + 1
+        return col == 7 ? a : b;
+    } else {
+        return nbr<DPP_WAVE_SHL1>(v);
+    }
+}
+
 // a wave-uniform value, made known as such to the compiler
 __device__ __forceinline__ int64_t uniform(int64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
@@ -517,7 +542,7 @@ constexpr int update_waves() { return SS::Q == 36 ? LB_WAVES36 : SS::Q == 16 ? 4
 template <class SS>
 constexpr int pair_waves() { return SS::Q == 36 ? LB_WAVES36_PAIR : update_waves<SS>(); }
 
-template <class ST, class SS, class OO, int WV, bool NW = false, int SPL = update_split<SS>()>
+template <class ST, class SS, class OO, int WV, bool NW = false, int SPL = update_split<SS>(), bool WR = false>
 __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
                                             const int j0, const int j1, const int lane, const int S = 0);
 
@@ -525,7 +550,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 // narrow lattice) 64 / (nx + 4) lane groups of nx + 4 columns each, group
 // g marching rows j0 + g S .. j0 + (g + 1) S (clipped to j1); SPL waves
 // share the populations (the result does not depend on SPL)
-template <class ST, class SS, class OO, bool NW = false, int SPL = update_split<SS>()>
+template <class ST, class SS, class OO, bool NW = false, int SPL = update_split<SS>(), bool WR = false>
 __device__ __forceinline__ void update_item(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
                                             const int j0, const int j1, const int S = 0) {
     constexpr int SPLIT = SPL;
@@ -534,17 +559,17 @@ __device__ __forceinline__ void update_item(const StepArgs &A, const int cur, co
     // for its own abscissae, so every population's upwind direction and
     // constants are known at compile time
     const int wv = SPLIT > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6) : 0;
-    if (wv == 0) update_rows<ST, SS, OO, 0, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
+    if (wv == 0) update_rows<ST, SS, OO, 0, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
     if constexpr (SPLIT > 1) {
-        if (wv == 1) update_rows<ST, SS, OO, 1, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 1) update_rows<ST, SS, OO, 1, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
     }
     if constexpr (SPLIT > 2) {
-        if (wv == 2) update_rows<ST, SS, OO, 2, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 2) update_rows<ST, SS, OO, 2, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
     }
     if constexpr (SPLIT > 3) {
-        if (wv == 3) update_rows<ST, SS, OO, 3, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
-        if (wv == 4) update_rows<ST, SS, OO, 4, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
-        if (wv == 5) update_rows<ST, SS, OO, 5, NW, SPL>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 3) update_rows<ST, SS, OO, 3, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 4) update_rows<ST, SS, OO, 4, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 5) update_rows<ST, SS, OO, 5, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
     }
 }
 
@@ -621,8 +646,10 @@ __device__ __forceinline__ void batch_item(const BatchMulti &M, const int slot, 
     // kernel's own stores change them, and reloads them per lane)
     const StepArgs &A = *(const StepArgs *)((const __attribute__((address_space(4))) StepArgs *)M.desc + l);
     // a negative first column marks a narrow lattice's item: -i0 rows per
-    // lane group
-    if (i0 < 0) update_item<ST, SS, SS, true, multi_split<SS>()>(A, M.cur, M.seed, 0, j0, j1, -i0);
+    // lane group, or -i0 - NW_WRAP for an 8-column periodic lattice whose
+    // x neighbours wrap inside 8-lane groups
+    if (i0 <= -NW_WRAP) update_item<ST, SS, SS, true, multi_split<SS>(), true>(A, M.cur, M.seed, 0, j0, j1, -i0 - NW_WRAP);
+    else if (i0 < 0) update_item<ST, SS, SS, true, multi_split<SS>()>(A, M.cur, M.seed, 0, j0, j1, -i0);
     else update_item<ST, SS, SS, false, multi_split<SS>()>(A, M.cur, M.seed, i0, j0, j1);
 }
 
@@ -666,7 +693,7 @@ void k_update_multi(const BatchMulti M) {
         }                                                                                \
     }
 
-template <class ST, class SS, class OO, int WV, bool NW, int SPL>
+template <class ST, class SS, class OO, int WV, bool NW, int SPL, bool WR>
 __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
                                             const int j0, const int j1, const int lane, const int S) {
     // multiply-adds are fused within an expression only (not across
@@ -694,7 +721,15 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     // side) marches its own rows [jl0, jl1); wide: one group, rows [j0, j1)
     int col, jl0 = j0, jl1 = j1;
     bool valid;
-    if constexpr (NW) {
+    if constexpr (WR) {
+        // 8-column periodic lattices: eight groups of eight lanes, the x
+        // neighbours wrapped inside the group (no halo lanes)
+        const int gl = lane >> 3;
+        col = lane & 7;
+        jl0 = min(j0 + gl * S, j1);
+        jl1 = min(jl0 + S, j1);
+        valid = true;
+    } else if constexpr (NW) {
         const int G = nx + 4, gl = lane / G;
         col = lane - gl * G - 2;
         jl0 = min(j0 + gl * S, j1);
@@ -925,14 +960,14 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 // takes L_i and its neighbour's from the adjacent lane
                 // (the same values as forming each face's slope in place)
                 if (xp != 0.0) {
-                    const T fm1 = nbr<DPP_WAVE_SHR1>(f);
-                    const T fp1 = nbr<DPP_WAVE_SHL1>(f);
+                    const T fm1 = xleft<WR>(f, col);
+                    const T fp1 = xright<WR>(f, col);
                     const T dm = f - fm1, dp = fp1 - f;
                     const T L = minmod(dm, dp);
                     if (xp > 0.0) {
-                        acc = acc - nu[p] * dm - kk[p] * (L - nbr<DPP_WAVE_SHR1>(L));
+                        acc = acc - nu[p] * dm - kk[p] * (L - xleft<WR>(L, col));
                     } else {
-                        acc = acc - nu[p] * dp - kk[p] * (nbr<DPP_WAVE_SHL1>(L) - L);
+                        acc = acc - nu[p] * dp - kk[p] * (xright<WR>(L, col) - L);
                     }
                 }
                 // y fluxes (register window)

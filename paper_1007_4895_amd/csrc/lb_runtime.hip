@@ -1439,12 +1439,16 @@ lb_status batch_build(lb_batch *B) {
                 set_runs(B->lat[l], s, runs, runcol);
                 // a lattice at most 28 columns wide packs 64 / (nx + 4) lane
                 // groups into a wave, each marching `strip` rows of its own;
-                // such items carry -strip as their first column
-                const int ng = 64 / (B->lat[l]->p.nx + 4);
+                // such items carry -strip as their first column.  An
+                // 8-column periodic lattice takes 8 groups of 8 lanes with
+                // the x neighbours wrapped in the group: -(strip + NW_WRAP)
+                const lb_lattice *La = B->lat[l];
+                const bool wrap = La->p.nx == 8 && La->p.xbc == LB_XBC_PERIODIC;
+                const int ng = wrap ? 8 : 64 / (La->p.nx + 4);
                 const int span = ng >= 2 ? ng * strip : strip;
                 for (size_t r = 0; r < runs.size(); ++r)
                     for (int j = runs[r].first; j < runs[r].second; j += span) {
-                        v.push_back(ng >= 2 ? -strip : runcol[r]);
+                        v.push_back(wrap ? -(strip + lbi::NW_WRAP) : ng >= 2 ? -strip : runcol[r]);
                         v.push_back(j);
                         v.push_back(std::min(j + span, runs[r].second));
                         v.push_back(s * nl + l);
