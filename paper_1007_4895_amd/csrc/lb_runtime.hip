@@ -93,8 +93,12 @@ Layout ws_layout(const lb_params &p) {
     const int nrow = p.ny + 1;
     const int n[2] = {p.n_low, p.n_high};
     size_t off = 0;
+    // rows start on 128-byte lines, except for lattices narrower than a
+    // line, whose rows are packed (16-byte steps) so that neighbouring rows
+    // share lines and the footprint is not mostly padding
+    const size_t row_al = size_t(p.nx + 4) * eb < 128 ? size_t(std::max(1, 16 / eb)) : size_t(al);
     for (int s = 0; s < 2; ++s) {
-        L.pitch[s] = int32_t(align_up(size_t(p.nx) + 4, al));
+        L.pitch[s] = int32_t(align_up(size_t(p.nx) + 4, row_al));
         L.rowbase[s] = al;
         L.plane[s] = int64_t(align_up(size_t(al) + size_t(nrow + 4) * L.pitch[s], al));
         size_t bytes = size_t(n[s] * n[s]) * size_t(L.plane[s]) * eb;
