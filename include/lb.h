@@ -300,8 +300,8 @@ lb_status lb_batch_set_graph(lb_batch *B, int32_t segment_steps);
 lb_status lb_batch_step(lb_batch *B, int64_t steps);
 
 /* Rows per work item of the low / high sets (0 = automatic), and the
- * autotuner that times candidates for `steps` steps each and keeps the
- * fastest (lattice states are restored). */
+ * autotuner that times candidates for `steps` steps each (twice, the faster
+ * pass counting) and keeps the fastest (lattice states are restored). */
 lb_status lb_batch_set_strip_rows(lb_batch *B, int32_t rows_low, int32_t rows_high);
 lb_status lb_batch_autotune(lb_batch *B, int32_t steps, int32_t rows_out[2]);
 
