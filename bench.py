@@ -104,6 +104,56 @@ def large_section(lb, W, torch, steps):
     return out
 
 
+def c3_section(lb, W, torch, segments=4):
+    """The pressure-driven channel (4096 x 257) as its workload runs: per
+    segment of `regrid` steps, then new per-tile bands from the indicator
+    (indicator, band rule, lift / restriction of the rows that switch set),
+    in FP32 and bf16 storage; and the same channel all-D2Q36 (FP32)."""
+    import numpy as np
+
+    from paper_1007_4895_amd import closure
+    c = W.PRESSURE_C3
+    nodes = c["nx"] * (c["ny"] + 1)
+    out = {"workload": f"pressure_c3: {c['nx']}x{c['ny'] + 1}, rho_in/rho_out {c['rho_in']}/{c['rho_out']}, outlet Kn "
+                       f"{c['kn']}, bands from the indicator every {c['regrid']} steps (theta {c['theta']}, "
+                       f"{c['bmin']}-{c['bmax']} rows per 64-column tile), D2Q9 / D2Q36 order 4",
+           "nodes": nodes, "timed_steps": segments * c["regrid"]}
+    for st in ("f32", "bf16"):
+        G = closure.channel(c["nx"], c["ny"], c["kn"], storage=st, all_high=False, bands=(c["bmin"], c["bmin"]),
+                            rho_in=c["rho_in"], rho_out=c["rho_out"], cfl=c["cfl"], tile_w=c["tile_w"])
+        G.step(c["regrid"])
+        G.update_regions(c["theta"], c["bmin"], c["bmax"])
+        G.autotune(50)
+        eb = 4 if st == "f32" else 2
+        alg = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(segments):
+            cnt = G.region_counts()
+            alg += c["regrid"] * eb * 2 * (9 * cnt[0] + 36 * cnt[1])
+            G.step(c["regrid"])
+            G.update_regions(c["theta"], c["bmin"], c["bmax"])
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        lo, hi = G.get_regions()
+        out[st] = {"mlups": round(nodes * segments * c["regrid"] / sec / 1e6, 1),
+                   "us_per_step": round(1e6 * sec / (segments * c["regrid"]), 2),
+                   "hbm_gbs_algorithmic": round(alg / sec / 1e9, 1),
+                   "mean_band_rows": round(float(np.mean(np.concatenate([lo, hi]))), 1)}
+        del G
+    G = closure.channel(c["nx"], c["ny"], c["kn"], storage="f32", all_high=True, rho_in=c["rho_in"],
+                        rho_out=c["rho_out"], cfl=c["cfl"], tile_w=c["tile_w"])
+    G.autotune(50)
+    G.step(100)
+    n = 2 * c["regrid"]
+    sec = timed(G, n, torch)
+    out["all_d2q36_f32"] = {"mlups": round(nodes * n / sec / 1e6, 1), "us_per_step": round(1e6 * sec / n, 2),
+                            "hbm_gbs_algorithmic": round(nodes * 36 * 8 * n / sec / 1e9, 1)}
+    out["speedup_f32_vs_all_d2q36"] = round(out["f32"]["mlups"] / out["all_d2q36_f32"]["mlups"], 3)
+    del G
+    return out
+
+
 def batch_section(lb, W, torch):
     """The 128-channel workload stepped as one batch (graph-captured
     segments, autotuned strips) against stepping each channel with its own
@@ -169,6 +219,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 128-channel batch section")
     ap.add_argument("--batch-only", action="store_true", help="run only the 128-channel batch section (profiling)")
     ap.add_argument("--no-large", action="store_true", help="skip the 4096-column (beyond the Infinity Cache) section")
+    ap.add_argument("--no-c3", action="store_true", help="skip the pressure-channel (regrid) section")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="steps of the kernel-timing pass (the dominant kernel's roofline)")
     ap.add_argument("--shape", type=str, default="",
@@ -335,6 +386,11 @@ def main():
     if not args.no_large:
         out["c2_wide_4096"] = large_section(lb, W, torch, 2000)
         print(f"wide: {out['c2_wide_4096']}", flush=True)
+
+    # ------------------- pressure channel with its periodic re-decomposition
+    if not args.no_c3:
+        out["pressure_c3"] = c3_section(lb, W, torch)
+        print(f"c3: {out['pressure_c3']}", flush=True)
 
     # ------------------- 128 independent channels: one batch vs one launch per case
     if not args.no_batch:
