@@ -20,6 +20,7 @@
 
 #include "../../include/lb.h"
 #include "lb_internal.hpp"
+#include "lb_lists.hpp"
 #include "lb_registry.hpp"
 #include "lb_tables.hpp"
 
@@ -150,12 +151,7 @@ const lbk::KernelSet *find_any(int nS, int eqS, int nO, int eqO) {
     return nullptr;
 }
 
-// region of node (i, j) for bands lo/hi of its tile; same rule as the kernels
-int host_reg(int lo, int hi, int j, int ny, int iface) {
-    if (j < lo || j > ny - hi) return REG_HIGH;
-    if (iface == IF_PAPER && ((lo > 0 && j == lo) || (hi > 0 && j == ny - hi))) return REG_IFACE;
-    return REG_LOW;
-}
+using lbl::host_reg;
 
 // Diffuse-wall constants of a set (Sec. 3.2): S = f_eq(rho = 1, u_wall) of
 // the set's order, stored as S' = S - w (computed without cancellation),
@@ -423,62 +419,12 @@ int build_items(const lb_lattice *L, int s, std::vector<int32_t> &out) {
     return int(out.size() / 4);
 }
 
-bool host_neighbour_in(const lb_lattice *L, int i, int j, int want) {
-    const int nx = L->p.nx, ny = L->p.ny, nrow = ny + 1;
-    auto reg = [&](int ii, int jj) {
-        int t = L->ntiles == 1 ? 0 : ii / L->tile_w;
-        return host_reg(L->blo[t], L->bhi[t], jj, ny, L->p.iface);
-    };
-    for (int d = -2; d <= 2; ++d) {
-        if (!d) continue;
-        int jj = j + d;
-        if (jj < 0 || jj > ny) {
-            if (L->p.ybc != LB_YBC_PERIODIC) continue;
-            jj = (jj + nrow) % nrow;
-        }
-        if (reg(i, jj) == want) return true;
-        int ii = i + d;
-        if (ii < 0 || ii >= nx) {
-            if (L->p.xbc != LB_XBC_PERIODIC) continue;
-            ii = (ii + nx) % nx;
-        }
-        if (reg(ii, j) == want) return true;
-    }
-    return false;
-}
 
-// Per-step lists: `fin` = nodes needing row images (periodic y) or pressure
-// columns, as (i, j, set, 0); `proj` = nodes a stencil of the partner set
-// reads (Hermite interface), as (i, j), low-set nodes first.
+// Per-step lists of a lattice (lbl::build_lists on its decomposition).
 int build_lists(const lb_lattice *L, std::vector<int32_t> &fin, std::vector<int32_t> &proj, int nproj[2]) {
-    fin.clear();
-    proj.clear();
-    std::vector<int32_t> ph;
-    const int nx = L->p.nx, ny = L->p.ny, nrow = ny + 1;
-    for (int j = 0; j < nrow; ++j)
-        for (int i = 0; i < nx; ++i) {
-            int t = L->ntiles == 1 ? 0 : i / L->tile_w;
-            int r = host_reg(L->blo[t], L->bhi[t], j, ny, L->p.iface);
-            if (r == REG_IFACE) continue;
-            const int set = r == REG_HIGH ? 1 : 0;
-            bool misc = (L->p.ybc == LB_YBC_PERIODIC && (j < 2 || j >= nrow - 2)) ||
-                        (L->p.xbc == LB_XBC_PRESSURE && (i == 0 || i == nx - 1));
-            if (misc) {
-                fin.push_back(i);
-                fin.push_back(j);
-                fin.push_back(set);
-                fin.push_back(0);
-            }
-            if (L->p.iface == LB_IFACE_HERMITE && host_neighbour_in(L, i, j, set ? REG_LOW : REG_HIGH)) {
-                std::vector<int32_t> &dst = set ? ph : proj;
-                dst.push_back(i);
-                dst.push_back(j);
-            }
-        }
-    nproj[0] = int(proj.size() / 2);
-    nproj[1] = int(ph.size() / 2);
-    proj.insert(proj.end(), ph.begin(), ph.end());
-    return int(fin.size() / 4);
+    const lbl::Decomp D{L->p.nx, L->p.ny, L->p.xbc, L->p.ybc, L->p.iface, L->ntiles, L->tile_w,
+                        L->blo.data(), L->bhi.data()};
+    return lbl::build_lists(D, fin, proj, nproj);
 }
 
 lb_status upload_regions(lb_lattice *L) {

@@ -339,6 +339,31 @@ def test_region_change_and_indicator(oracle, lb):
     np.testing.assert_array_equal(bg[1], bo[1])
 
 
+def test_empty_wall_band_next_to_band(oracle, lb):
+    # one tile has no high-set rows at a wall (band 0), its neighbour has a
+    # band there: wall-row nodes beside the tile boundary are read across x
+    # by the other set and must be projected although their y neighbours
+    # beyond the wall do not exist
+    nx, ny = 128, 32
+    O, G = pair(oracle, lb, nx, ny, n_low=3, eq_low=2, n_high=6, eq_high=4, kn=0.1, tile_w=64,
+                u_wall=((-0.05, 0.0), (0.05, 0.0)), bands=(6, 6), cfl=0.3)
+    O.init_equilibrium()
+    G.init_equilibrium()
+    O.step(40)
+    G.step(40)
+    lo, hi = np.array([0, 7], np.int32), np.array([5, 0], np.int32)
+    O.update_regions(lo, hi)
+    G.change_regions(lo, hi)
+    O.step(30)
+    G.step(30)
+    for s in (0, 1):
+        e, m = pop_err(G, O, s)
+        assert m > 0 and e < 1e-12
+    _, uxo, uyo = O.moments()
+    _, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-12
+
+
 # ----------------------------------------------- pressure channel with regrid
 def _c3_small(oracle, lb, storage, regrid):
     nx, ny, tw = 256, 48, 64
