@@ -220,6 +220,7 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="run only the 128-channel batch section (profiling)")
     ap.add_argument("--no-large", action="store_true", help="skip the 4096-column (beyond the Infinity Cache) section")
     ap.add_argument("--no-c3", action="store_true", help="skip the pressure-channel (regrid) section")
+    ap.add_argument("--c3-only", action="store_true", help="run only the pressure-channel section (profiling)")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="steps of the kernel-timing pass (the dominant kernel's roofline)")
     ap.add_argument("--shape", type=str, default="",
@@ -242,6 +243,9 @@ def main():
     torch.cuda.init()
     if args.batch_only:
         print(json.dumps({"batch_c5": batch_section(lb, W, torch)}))
+        return
+    if args.c3_only:
+        print(json.dumps({"pressure_c3": c3_section(lb, W, torch)}))
         return
 
     if args.copy_calib:

@@ -22,6 +22,9 @@ struct Inst {
     static void project_halo(const StepArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_project_halo<ST, S, O>), dim3(grid), dim3(128), 0, s, a);
     }
+    static void project_finish(const StepArgs &a, const int32_t *fin, int nfin, int nbp, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_project_finish<ST, S, O>), dim3(grid), dim3(128), 0, s, a, fin, nfin, nbp);
+    }
     static void closure_infer(const StepArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_closure_infer<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
     }
@@ -82,6 +85,7 @@ struct Inst {
         k.update_timed = &update_timed;
         k.finish = &finish;
         k.project_halo = &project_halo;
+        k.project_finish = &project_finish;
         k.refresh = &refresh;
         k.init_eq = &init_eq;
         k.set_pop = &set_pop;

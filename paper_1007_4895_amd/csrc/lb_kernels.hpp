@@ -1266,10 +1266,9 @@ __device__ __forceinline__ void project_entry(const StepArgs &A, const int cur, 
     }
 }
 
-// one thread per (node, target column)
+// thread k of the projection pass: one per (node, target column)
 template <class ST, class LS, class HS>
-__global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void project_halo_thread(const StepArgs &A, const int64_t k) {
     const int64_t n0 = (int64_t)A.nitems * HS::N, n1 = (int64_t)A.chunk * LS::N;
     if (k < n0) {
         const int e = int(k / HS::N), tq = int(k % HS::N);
@@ -1279,6 +1278,31 @@ __global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
         const int e = int((k - n0) / LS::N) + A.nitems, tq = int((k - n0) % LS::N);
         project_entry<ST, LS, HS>(A, A.cur, false, A.items[2 * e], A.items[2 * e + 1], tq, nullptr);
     }
+}
+
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_project_halo(const StepArgs A) {
+    project_halo_thread<ST, LS, HS>(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The projection and finish passes of one step in one launch: blocks below
+// nbp project (as k_project_halo), the rest finish the nodes of `fin` (as
+// k_finish).  Both read only the updated copy, and their writes are
+// disjoint: a projection writes the partner set's entries of a node and
+// their ghosts/images, the finish pass a node's own set's ghosts, images and
+// pressure columns, and no node belongs to both sets.
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(128) void k_project_finish(const StepArgs A, const int32_t *fin, const int nfin,
+                                                        const int nbp) {
+    if ((int)blockIdx.x < nbp) {
+        project_halo_thread<ST, LS, HS>(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+        return;
+    }
+    constexpr int QM = finish_qmax<LS, HS>();
+    const int k = ((int)blockIdx.x - nbp) * blockDim.x + threadIdx.x;
+    const int e = k / QM;
+    if (e >= nfin) return;
+    finish_pop<ST, LS, HS>(A, A.cur, fin[4 * e], fin[4 * e + 1], fin[4 * e + 2], k % QM);
 }
 
 // batch form: items (i, j, l, 0) of lattice l, whose arguments (self = low

@@ -16,6 +16,8 @@ using NodeFn = void (*)(const lbi::NodeArgs &, int grid, hipStream_t);
 using IfaceFn = void (*)(const lbi::NodeArgs &, int copy, int recompute, int grid, hipStream_t);
 using ProjFn = void (*)(const double *, const double *, double *, int64_t, hipStream_t);
 using BatchFn = void (*)(const lbi::BatchArgs &, int grid, hipStream_t);
+// projection (nb_proj blocks) and finish pass over `fin` (nfin entries) in one launch
+using ProjFinFn = void (*)(const lbi::StepArgs &, const int32_t *fin, int nfin, int nb_proj, int grid, hipStream_t);
 // both sets' updates in one launch (self = low set, D2Q9 only): the blocks
 // of the high set come first
 using PairFn = void (*)(const lbi::StepArgs &low, const lbi::StepArgs &high, int nb_high, int nb_low, hipStream_t,
@@ -27,6 +29,7 @@ struct KernelSet {
     TimedFn update_timed;   // the same launch bracketed by kernel start/stop events
     StepFn finish;        // valid when `self` is the low set of the pair
     StepFn project_halo;  // likewise
+    ProjFinFn project_finish;   // likewise
     NodeFn refresh, init_eq, set_pop, get_pop, moments, indicator, convert;
     IfaceFn paper_iface;   // valid when `self` is the low set of the pair
     ProjFn project;        // FP64 projection self -> partner

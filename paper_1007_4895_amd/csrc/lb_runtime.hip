@@ -576,6 +576,7 @@ lb_status one_step(lb_lattice *L) {
     }
     a.self = L->buf[0];
     a.other = L->buf[1];
+    bool fin_done = false;
     if (L->nproj[0] + L->nproj[1]) {
         a.items = L->d_proj;
         a.nitems = L->nproj[0];
@@ -598,16 +599,25 @@ lb_status one_step(lb_lattice *L) {
             if (L->nproj[1])
                 L->ks[0]->project_halo(down, int((int64_t(L->nproj[1]) * L->n[0] + 127) / 128), L->stream);
         } else {
-            // one thread per (node, target column)
+            // one thread per (node, target column); with a finish list, its
+            // pass joins the same launch (one thread per node and population)
             const int64_t nt = int64_t(L->nproj[0]) * L->n[1] + int64_t(L->nproj[1]) * L->n[0];
-            L->ks[0]->project_halo(a, int((nt + 127) / 128), L->stream);
+            const int nbp = int((nt + 127) / 128);
+            if (L->nfin) {
+                const int qm = std::max(L->Q[0], L->Q[1]);
+                const int nbf = int((int64_t(L->nfin) * qm + 127) / 128);
+                L->ks[0]->project_finish(a, L->d_fin, L->nfin, nbp, nbp + nbf, L->stream);
+                fin_done = true;
+            } else {
+                L->ks[0]->project_halo(a, nbp, L->stream);
+            }
         }
     }
     if (par) {
         HIPCHK(hipEventRecord(L->ejoin, L->side));
         HIPCHK(hipStreamWaitEvent(L->stream, L->ejoin, 0));
     }
-    if (L->nfin) {
+    if (L->nfin && !fin_done) {
         a.items = L->d_fin;
         a.nitems = L->nfin;
         const int qm = std::max(L->Q[0], L->Q[1]);   // one thread per (node, population)
