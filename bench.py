@@ -33,10 +33,15 @@ KERNEL_SOURCES = ["lb_kernels.hpp", "lb_tables.hpp", "lb_internal.hpp", "lb_inst
 
 
 def kernel_hash() -> str:
+    """Hash of the kernel's code: the sources without their // comments and
+    blank lines, so that an edit of a comment keeps recorded counters."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1007_4895_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1007_4895_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

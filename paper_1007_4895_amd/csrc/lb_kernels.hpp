@@ -7,20 +7,22 @@
 // with the TVD/minmod face values of Sec. 3.1, the order-N Hermite
 // equilibrium of Eq. (approxfeq) and the Hermite body force (Sec. 2.1).
 //
-// Mapping: one wave = 64 consecutive columns x a strip of rows.  Each lane
-// owns one column and marches up the strip keeping, per population, the
-// values and limited slopes it needs along y in registers, so every
-// population value is loaded from HBM once per step.  The x neighbours come
-// from the neighbouring lanes through DPP wave shifts; the two columns
-// beyond each side of the wave come from one 4-lane halo load.  The minmod
-// limited slope Delta+ Psi(Delta-/Delta+) is evaluated as med3(Delta-,
-// Delta+, 0), which is the same function.
+// Mapping: a work item is 60 consecutive columns x a strip of rows; its
+// waves load 64 columns (two halo columns on each side) and each lane
+// marches up one column keeping, per population, the values and limited
+// slopes it needs along y in registers, so every population value is loaded
+// from HBM once per strip.  The x neighbours come from the neighbouring
+// lanes through DPP wave shifts.  The minmod limited slope
+// Delta+ Psi(Delta-/Delta+) is evaluated as med3(Delta-, Delta+, 0), which
+// is the same function.  Diffuse walls (Sec. 3.2), wall ghost rows and
+// periodic image columns are written by the kernel that updates the node.
 //
-// Nodes with extra duties -- wall rows (diffuse reflection, Sec. 3.2),
-// ghost and row images, pressure columns, nodes that a stencil of the
-// partner set reads (Hermite projection, Sec. 2.2 in moment form) -- are
-// finished by k_finish, a node-local FP64 pass over a list of those nodes,
-// so that the hot kernel carries none of that register footprint.
+// Nodes with other duties -- periodic row images, pressure columns
+// (k_finish), and nodes that a stencil of the partner set reads (Hermite
+// projection, Sec. 2.2 in moment form: k_project_halo) -- are finished by
+// node-local FP64 passes over lists of those nodes, one launch for both
+// (k_project_finish) when a lattice has both lists, so that the hot kernel
+// carries none of that register footprint.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
