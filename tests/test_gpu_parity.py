@@ -124,6 +124,30 @@ def test_coupled_hermite_2d(oracle, lb, lo, hi):
     assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
 
 
+def test_coupled_periodic_y_tile_bands(oracle, lb):
+    # periodic in both directions with high-set bands that differ per tile:
+    # row images and Hermite projection entries in the same step (one
+    # launch for both), projection sources found across the y wrap
+    nx, ny, tw = 130, 40, 64
+    O, G = pair(oracle, lb, nx, ny, n_low=3, eq_low=2, n_high=6, eq_high=4, kn=0.08, gx=5e-5, gy=-2e-5,
+                ybc=oracle.YBC_PERIODIC, tile_w=tw, bands=(5, 5), cfl=0.3)
+    rho, ux, uy = W.smooth_fields(nx, ny + 1, seed=37)
+    O.init_equilibrium(rho, ux, uy)
+    G.init_equilibrium(rho, ux, uy)
+    lo, hi = np.array([4, 0, 7], np.int32), np.array([2, 6, 0], np.int32)
+    O.update_regions(lo, hi)
+    G.change_regions(lo, hi)
+    for k in (1, 25):
+        O.step(k)
+        G.step(k)
+        for s in (0, 1):
+            e, m = pop_err(G, O, s)
+            assert m > 0 and e < 1e-11, (k, s, e)
+    r_o, uxo, uyo = O.moments()
+    r_g, uxg, uyg = G.moments()
+    assert rel_u(uxg, uyg, uxo, uyo) < 1e-10
+
+
 def test_couette_c1_full_run(oracle, lb):
     c = W.COUETTE_C1
     O, G = pair(oracle, lb, c["nx"], c["ny"], n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"],
