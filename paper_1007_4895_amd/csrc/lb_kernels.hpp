@@ -942,6 +942,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
             }
             const double xq = TB::rule.x[q];
             T nq = T(0);
+            T accq[N];   // this y-abscissa's updated values of the row
 #pragma unroll
             for (int p = 0; p < N; ++p) {
                 const int k = p + N * qq;
@@ -994,23 +995,34 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 nw[k] = ST::bld(rs, LB_VO(vln, xq < 0.0 ? j + 3 : j + 2), LB_SO(a, xq < 0.0 ? j + 3 : j + 2));
 
                 LB_ST(LB_VO(vs, j), LB_SO(a, j), acc)
-                if (wave_img) {
-                    LB_ST(LB_VO(vimg_lo, j), LB_SO(a, j), acc)
-                    LB_ST(LB_VO(vimg_hi, j), LB_SO(a, j), acc)
-                }
-                if (wall) {
-                    // into the wall: bottom xi_y < 0, top xi_y > 0; those and
-                    // xi_y = 0 are final: copy them to the ghost rows
-                    const bool leaving = bottom ? (xq > 0.0) : (xq < 0.0);
-                    if (!leaving) {
-                        if (xq != 0.0) nq += T(lbt::cabs(xq)) * acc;
-                        LB_ST(LB_VO(vw, gj1), LB_SO(a, gj1), acc)
-                        LB_ST(LB_VO(vw, gj2), LB_SO(a, gj2), acc)
-                    }
-                }
+                accq[p] = acc;
                 // keep the scheduler from hoisting every population's
                 // neighbour arithmetic to the top of the row (register blow-up)
                 __builtin_amdgcn_sched_barrier(0);
+            }
+            // image columns and wall ghosts of this y-abscissa's populations:
+            // one wave-uniform branch each per abscissa, not per population
+            if (wave_img) {
+#pragma unroll
+                for (int p = 0; p < N; ++p) {
+                    const int a = p + N * q;
+                    LB_ST(LB_VO(vimg_lo, j), LB_SO(a, j), accq[p])
+                    LB_ST(LB_VO(vimg_hi, j), LB_SO(a, j), accq[p])
+                }
+            }
+            if (wall) {
+                // into the wall: bottom xi_y < 0, top xi_y > 0; those and
+                // xi_y = 0 are final: copy them to the ghost rows
+                const bool leaving = bottom ? (xq > 0.0) : (xq < 0.0);
+                if (!leaving) {
+#pragma unroll
+                    for (int p = 0; p < N; ++p) {
+                        const int a = p + N * q;
+                        if (xq != 0.0) nq += T(lbt::cabs(xq)) * accq[p];
+                        LB_ST(LB_VO(vw, gj1), LB_SO(a, gj1), accq[p])
+                        LB_ST(LB_VO(vw, gj2), LB_SO(a, gj2), accq[p])
+                    }
+                }
             }
             if (wall) {
                 if constexpr (SPLIT > 1) sn[bottom ? 0 : 1][q][lane] = nq;
