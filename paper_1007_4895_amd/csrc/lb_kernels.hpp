@@ -239,6 +239,13 @@ __device__ __forceinline__ int reg_of(int lo, int hi, int j, const Geo &g) {
     if (g.iface == IF_PAPER && ((lo > 0 && j == lo) || (hi > 0 && j == g.ny - hi))) return REG_IFACE;
     return REG_LOW;
 }
+// the same rule with non-short-circuit operators: per-lane bands compile to
+// selects instead of a divergent branch (a few more registers)
+__device__ __forceinline__ int reg_of_sel(int lo, int hi, int j, const Geo &g) {
+    const bool high = (j < lo) | (j > g.ny - hi);
+    const bool ifc = (g.iface == IF_PAPER) & (((lo > 0) & (j == lo)) | ((hi > 0) & (j == g.ny - hi)));
+    return high ? REG_HIGH : (ifc ? REG_IFACE : REG_LOW);
+}
 __device__ __forceinline__ int tile_of(int i, const Geo &g) { return g.ntiles == 1 ? 0 : i / g.tile_w; }
 __device__ __forceinline__ int region_at(int i, int j, const Geo &g) {
     int t = tile_of(i, g);
@@ -844,7 +851,10 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
         const int j = NW ? jl0 + jr : jr;
         const bool more = jr + 1 < (NW ? S : j1);
         const unsigned vln = more ? vl : OOB;
-        const bool own = valid && (!NW || j < jl1) && reg_of(lo_l, hi_l, j, g) == want;
+        // (without short-circuit: selects, not a divergent branch, for the
+        // sets whose register budget leaves room; D2Q36 would spill)
+        const int rj = Q < 36 ? reg_of_sel(lo_l, hi_l, j, g) : reg_of(lo_l, hi_l, j, g);
+        const bool own = valid & (!NW || j < jl1) & (rj == want);
         const unsigned vs = own ? unsigned(col + 2) * EB : OOB;
         const unsigned vimg_lo = (per_x && own && col < 2) ? unsigned(col + nx + 2) * EB : OOB;
         const unsigned vimg_hi = (per_x && own && col >= nx - 2) ? unsigned(col - nx + 2) * EB : OOB;
