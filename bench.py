@@ -226,6 +226,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 4096-column (beyond the Infinity Cache) section")
     ap.add_argument("--no-c3", action="store_true", help="skip the pressure-channel (regrid) section")
     ap.add_argument("--c3-only", action="store_true", help="run only the pressure-channel section (profiling)")
+    ap.add_argument("--large-only", action="store_true", help="run only the 4096-column section (profiling)")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="steps of the kernel-timing pass (the dominant kernel's roofline)")
     ap.add_argument("--shape", type=str, default="",
@@ -251,6 +252,9 @@ def main():
         return
     if args.c3_only:
         print(json.dumps({"pressure_c3": c3_section(lb, W, torch)}))
+        return
+    if args.large_only:
+        print(json.dumps({"c2_wide_4096": large_section(lb, W, torch, 2000)}))
         return
 
     if args.copy_calib:
