@@ -515,6 +515,30 @@ def test_concurrent_streams_bit_identical(lb):
         assert np.array_equal(a[m], b[m]), s
 
 
+def test_project_finish_launch_bit_identical(lb):
+    # a pressure channel with tile bands has both a projection list and
+    # pressure columns: one merged launch (single stream) against the
+    # separate projection and finish kernels (second stream)
+    nx, ny = 256, 48
+    Ls = []
+    for conc in (True, False):
+        p = lb.make_params(nx, ny, kn=0.2, n_low=3, eq_low=2, n_high=6, eq_high=4, storage="f32",
+                           xbc=lb.XBC_PRESSURE, rho_in=2.0, rho_out=1.0, tau_mode=lb.TAU_RHO, tile_w=64, cfl=0.3)
+        L = lb.Lattice(p)
+        L.set_regions(np.array([8, 12, 6, 10], np.int32), np.array([9, 5, 11, 8], np.int32))
+        xx = np.arange(nx)[None, :] * np.ones((ny + 1, 1))
+        L.init_equilibrium(2.0 - xx / (nx - 1), 0 * xx, 0 * xx)
+        L.set_concurrency(conc)
+        Ls.append(L)
+    for L in Ls:
+        L.step(40)
+    for s in (0, 1):
+        a, b = Ls[0].get_populations(s), Ls[1].get_populations(s)
+        assert np.array_equal(np.isnan(a), np.isnan(b))
+        m = ~np.isnan(a)
+        assert m.sum() > 0 and np.array_equal(a[m], b[m]), s
+
+
 def test_c3_full_size_regrid_bands(oracle, lb):
     # the pressure channel at its full size (4096 x 257, FP32, Courant 0.3):
     # at every regrid (each 500 steps) the bands the GPU derives from its
