@@ -238,6 +238,21 @@ size_t lb_mlp_workspace_bytes(int64_t n);
 /* y[n][8] = network(x[n][10]) in FP32. */
 lb_status lb_mlp_forward(const float *params, const float *x, float *y, int64_t n, void *ws, void *hip_stream);
 
+/* Allocation-free variant of lb_mlp_forward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same kernels and results,
+ * with the hidden activations in a library-owned device array of
+ * 2 x 64 x LB_MLP_NOALLOC_MAX_N floats (8 MiB) that each GPU holds until the
+ * process ends, in place of the caller's workspace.  n above
+ * LB_MLP_NOALLOC_MAX_N is rejected with LB_EINVAL before anything is
+ * enqueued.  The stream must belong to the current device.  Calls share
+ * that device's array: calls that overlap on one GPU (other streams, other
+ * host threads) race and must be ordered by the caller.  Nothing in the
+ * array needs clearing: each layer writes its rows before the next reads
+ * them.  Calls no hipMalloc / hipFree. */
+#define LB_MLP_NOALLOC_MAX_N 16384
+lb_status lb_mlp_forward_noalloc(const float *params, const float *x, float *y, int64_t n, void *hip_stream);
+
 /* Gradient of the batch mean of [squared error of the 6 regression outputs
  * / 6 + cross-entropy of the 2 flag logits]; loss = that mean (device
  * float).  Deterministic. */

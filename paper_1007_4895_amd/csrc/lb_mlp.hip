@@ -7,6 +7,8 @@
 // thread, so gradients are deterministic.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "../../include/lb.h"
 #include "lb_kernels.hpp"
 #include "lb_registry.hpp"
@@ -139,6 +141,49 @@ __global__ __launch_bounds__(64) void k_closure_eval(const uint16_t *w, ClosureN
 
 int blocks(int64_t n, int t = 256) { return int((n + t - 1) / t); }
 
+// the three dense layers of the forward pass; H1, H2 hold n x 64 floats each
+void forward_launch(const float *params, const float *x, float *y, int64_t n, float *H1, float *H2, hipStream_t s) {
+    const float *W1 = params, *b1 = params + MLP_OFF_B1, *W2 = params + MLP_OFF_W2, *b2 = params + MLP_OFF_B2;
+    const float *W3 = params + MLP_OFF_W3, *b3 = params + MLP_OFF_B3;
+    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 64)), dim3(256), 0, s, x, 10, W1, b1, H1, 64, n, 1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 64)), dim3(256), 0, s, H1, 64, W2, b2, H2, 64, n, 1);
+    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 8)), dim3(256), 0, s, H2, 64, W3, b3, y, 8, n, 0);
+}
+
+}  // namespace
+
+// Hidden activations of the allocation-free forward pass: two layers of
+// LB_MLP_NOALLOC_MAX_N x 64 floats (8 MiB), one copy per GPU for the life of
+// the process.  Host code never uses this name as an address: the device
+// address of each GPU's copy comes from hipGetSymbolAddress.
+static __device__ __align__(256) float scratch[2 * 64 * LB_MLP_NOALLOC_MAX_N];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device, looked up once per
+// device with that device current (nullptr on failure, error text set)
+float *scratch_on_current_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        lb_internal_fail(LB_EDEVICE, "no current HIP device for the allocation-free forward pass");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            lb_internal_fail(LB_EDEVICE, "hipGetSymbolAddress of the forward-pass scratch array failed");
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 namespace lbk {
@@ -155,14 +200,23 @@ size_t lb_mlp_workspace_bytes(int64_t n) { return size_t(n > 0 ? n : 0) * 273 * 
 
 lb_status lb_mlp_forward(const float *params, const float *x, float *y, int64_t n, void *ws, void *stream) {
     if (!params || !x || !y || !ws || n < 0) return lb_internal_fail(LB_EINVAL, "bad argument");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    float *H1 = reinterpret_cast<float *>(ws), *H2 = H1 + n * 64;
-    const float *W1 = params, *b1 = params + MLP_OFF_B1, *W2 = params + MLP_OFF_W2, *b2 = params + MLP_OFF_B2;
-    const float *W3 = params + MLP_OFF_W3, *b3 = params + MLP_OFF_B3;
     if (n == 0) return LB_OK;
-    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 64)), dim3(256), 0, s, x, 10, W1, b1, H1, 64, n, 1);
-    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 64)), dim3(256), 0, s, H1, 64, W2, b2, H2, 64, n, 1);
-    hipLaunchKernelGGL(k_dense, dim3(blocks(n * 8)), dim3(256), 0, s, H2, 64, W3, b3, y, 8, n, 0);
+    float *H1 = reinterpret_cast<float *>(ws), *H2 = H1 + n * 64;
+    forward_launch(params, x, y, n, H1, H2, reinterpret_cast<hipStream_t>(stream));
+    return hipGetLastError() == hipSuccess ? LB_OK : lb_internal_fail(LB_EDEVICE, "mlp forward launch failed");
+}
+
+lb_status lb_mlp_forward_noalloc(const float *params, const float *x, float *y, int64_t n, void *stream) {
+    if (!params || !x || !y || n < 0) return lb_internal_fail(LB_EINVAL, "bad argument");
+    if (n > LB_MLP_NOALLOC_MAX_N)
+        return lb_internal_fail(LB_EINVAL, "batch above LB_MLP_NOALLOC_MAX_N (16384 rows) for the allocation-free "
+                                           "forward pass; use lb_mlp_forward with a workspace");
+    if (n == 0) return LB_OK;
+    float *base = scratch_on_current_device();
+    if (!base) return LB_EDEVICE;
+    // every hidden value is written by its layer before the next layer
+    // reads it, so nothing in the array has to start at zero
+    forward_launch(params, x, y, n, base, base + 64 * LB_MLP_NOALLOC_MAX_N, reinterpret_cast<hipStream_t>(stream));
     return hipGetLastError() == hipSuccess ? LB_OK : lb_internal_fail(LB_EDEVICE, "mlp forward launch failed");
 }
 

@@ -94,6 +94,7 @@ def lib():
             "lb_mlp_param_count": (C.c_int64, []),
             "lb_mlp_workspace_bytes": (C.c_size_t, [C.c_int64]),
             "lb_mlp_forward": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp]),
+            "lb_mlp_forward_noalloc": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp]),
             "lb_mlp_loss_grad": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, _vp, _vp, _vp, _vp]),
             "lb_mlp_adam": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, C.c_float, _vp]),
             "lb_closure_eval": (C.c_int, [_vp, C.POINTER(C.c_float), C.c_double, C.c_int32, C.c_double, _vp,
@@ -449,6 +450,17 @@ class MLP:
         self.t += 1
         _check(lib().lb_mlp_adam(_vp(self.params.data_ptr()), _vp(self.grad.data_ptr()), _vp(self.m.data_ptr()),
                                  _vp(self.v.data_ptr()), self.t, lr, _stream(self.params, self.stream)))
+
+
+MLP_NOALLOC_MAX_N = 16384
+
+
+def mlp_forward_noalloc(params, x, y, stream=None):
+    """y[n, 8] = network(x[n, 10]) through the allocation-free entry point
+    (float32 device tensors; n <= MLP_NOALLOC_MAX_N)."""
+    _check(lib().lb_mlp_forward_noalloc(_vp(params.data_ptr()), _vp(x.data_ptr()), _vp(y.data_ptr()),
+                                        x.shape[0], _stream(x, stream)))
+    return y
 
 
 def closure_eval(params, norm, kn_ref, tau_rho, rho_ref, f9, stream=None):
