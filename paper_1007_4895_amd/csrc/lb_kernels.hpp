@@ -754,6 +754,18 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     // the wave-uniform offset of (population, row) in a scalar register.
     // Lanes that must not store get an offset past the end of the buffer,
     // which the hardware turns into a dropped store (or a zero load).
+    // Why this does not depend on how the compiler distributes an address
+    // over the vector, scalar and immediate offset fields: the host refuses
+    // lattices whose population buffer per set and copy reaches 2^31 bytes,
+    // so nbytes, every in-range byte offset and every scalar offset are
+    // below 2^31.  An in-range access has a total offset below nbytes
+    // whatever part of it sits in which field; a masked access has a vector
+    // part of at least nbytes (OOB, plus a non-negative row offset below
+    // 2^31 for narrow lattices), so vector + immediate (+ scalar, where the
+    // check counts it) stays in [nbytes, 2^32): it cannot wrap into range.
+    // Moving a uniform term between fields only adds a non-negative amount
+    // below 2^31 to the vector part; per-lane selects cannot move to the
+    // scalar field.
     // (the lattice's arguments are wave-uniform; a batch reads them from a
     // device table, so they are declared uniform here: the descriptor and
     // the scalar offsets must live in scalar registers)

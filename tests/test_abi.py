@@ -112,3 +112,16 @@ def test_null_arguments_are_rejected(lbmod):
     assert L.lb_mlp_workspace_bytes(1000) >= 4 * 1000 * (2 * 64 + 2 * 8 + 2 * 64 + 1)
     assert L.lb_set_work_shape(None, None, None) == EINVAL
     assert "bad argument" in L.lb_last_error().decode() or "null" in L.lb_last_error().decode()
+
+
+def test_two_gib_population_buffer_guard(lbmod):
+    # the update kernel masks lanes with buffer offsets past the end of a
+    # set's population buffer; that is only sound while every offset fits
+    # in 31 bits, so the host refuses lattices whose buffer per set and copy
+    # reaches 2 GiB (FP32 D2Q36: 36 planes of (nx + 4 rounded to 32) x (ny + 5))
+    L = lbmod.lib()
+    ok = lbmod.make_params(nx=4096, ny=3200, kn=0.1, n_low=6, n_high=6, eq_low=4, storage="f32")
+    assert L.lb_workspace_bytes(C.byref(ok)) > 0
+    big = lbmod.make_params(nx=4096, ny=3700, kn=0.1, n_low=6, n_high=6, eq_low=4, storage="f32")
+    assert L.lb_workspace_bytes(C.byref(big)) == 0
+    assert "2 GiB" in L.lb_last_error().decode()
