@@ -182,12 +182,16 @@ REG_LOW, REG_HIGH, REG_IFACE = 0, 1, 2
 
 class Lattice:
     """Oracle lattice: two velocity sets (low, high), bands of the high set at
-    each wall per column tile, rows 0..ny.  Populations are [Q][ny+1][nx]."""
+    each wall per column tile, rows 0..ny.  Populations are [Q][ny+1][nx].
+    u_osc, omega_osc: the bottom wall also moves along x with
+    u_osc sin(omega_osc t), t the time of the level being computed
+    (oscillatory Couette flow, Sec. 3.5)."""
 
     def __init__(self, nx, ny, *, kn, n_low=3, n_high=3, eq_low=2, eq_high=None,
                  force_low=None, force_high=None, dt=None, rho_ref=1.0, tau_mode=TAU_CONST,
                  gx=0.0, gy=0.0, u_wall=((0.0, 0.0), (0.0, 0.0)), xbc=XBC_PERIODIC,
-                 ybc=YBC_WALLS, rho_in=1.0, rho_out=1.0, iface=IFACE_HERMITE, tile_w=None):
+                 ybc=YBC_WALLS, rho_in=1.0, rho_out=1.0, iface=IFACE_HERMITE, tile_w=None,
+                 u_osc=0.0, omega_osc=0.0):
         eq_high = eq_low if eq_high is None else eq_high
         force_low = eq_low if force_low is None else force_low
         force_high = eq_high if force_high is None else force_high
@@ -201,7 +205,7 @@ class Lattice:
         self.tile_w = tile_w
         self.ntiles = (nx + tile_w - 1) // tile_w
         dp = np.array([kn, rho_ref, dt, gx, gy, u_wall[0][0], u_wall[0][1], u_wall[1][0],
-                       u_wall[1][1], rho_in, rho_out], dtype=np.float64)
+                       u_wall[1][1], rho_in, rho_out, u_osc, omega_osc], dtype=np.float64)
         ip = np.array([nx, ny, n_low, n_high, eq_low, eq_high, force_low, force_high,
                        tau_mode, xbc, ybc, iface, tile_w], dtype=np.int32)
         self._h = lib().lbo_create(_d(dp), _i(ip))
