@@ -72,6 +72,10 @@ typedef struct lb_params {
     double gx, gy;             /* body force per unit mass */
     double u_wall[4];          /* bottom (x, y), top (x, y) wall velocity */
     double rho_in, rho_out;    /* pressure x-boundary densities (LB_XBC_PRESSURE) */
+    double u_osc, omega_osc;   /* oscillating bottom wall (oscillatory Couette flow,
+                                  Sec. 3.5): its x velocity is u_wall[0] +
+                                  u_osc sin(omega_osc t), with t = (n + 1) dt when
+                                  step n -> n + 1 applies the wall condition */
 } lb_params;
 
 typedef struct lb_lattice lb_lattice;
@@ -114,7 +118,9 @@ lb_status lb_get_regions(const lb_lattice *L, int32_t *band_lo, int32_t *band_hi
 lb_status lb_init_equilibrium(lb_lattice *L, const double *rho, const double *ux, const double *uy);
 
 /* Advance nsteps time steps (Sec. 3.1 update, Sec. 3.2 walls, Sec. 2.2
- * interface).  Asynchronous on the lattice stream. */
+ * interface).  Asynchronous on the lattice stream.  With an oscillating
+ * bottom wall, the host recomputes that wall's equilibrium sums for every
+ * step (time-dependent kernel arguments, no device-side state). */
 lb_status lb_step(lb_lattice *L, int64_t nsteps);
 
 /* Density and velocity of every node ([ny+1][nx], FP64; interface rows report
@@ -298,7 +304,9 @@ lb_status lb_set_closure(lb_lattice *L, const float *params, const float *norm);
  *
  * The lattices stay owned by the caller and must outlive the batch; they
  * must share a storage type, use the Hermite interface, have no learned
- * closure set and be at the same copy parity (same step count modulo 2).
+ * closure set and no oscillating wall (graph replays repeat the captured
+ * kernel arguments), and be at the same copy parity (same step count
+ * modulo 2).
  * A lattice stepped on its own in between makes lb_batch_step fail with
  * LB_ESTATE; region changes are picked up (the work lists are rebuilt).
  * The batch allocates its descriptor table and work lists with hipMalloc.

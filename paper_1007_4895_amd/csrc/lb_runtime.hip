@@ -516,7 +516,22 @@ lb_status make_side_stream(lb_lattice *L) {
     return LB_OK;
 }
 
+// Wall constants of both sets for the wall velocities of time level
+// t = (step + 1) dt: the oscillating bottom wall (oscillatory Couette flow,
+// Sec. 3.5) adds u_osc sin(omega_osc t) to its x velocity.
+void set_wall_constants(lb_lattice *L, int64_t step) {
+    double uw[4];
+    for (int k = 0; k < 4; ++k) uw[k] = L->p.u_wall[k];
+    if (L->p.u_osc != 0.0) uw[0] += L->p.u_osc * std::sin(L->p.omega_osc * double(step + 1) * L->dt);
+    for (int s = 0; s < 2; ++s) {
+        double x[8] = {0}, w[8] = {0};
+        abscissae(L->n[s], x, w);
+        wall_constants(L->n[s], L->eq[s], x, w, uw, L->kconst[s]);
+    }
+}
+
 lb_status one_step(lb_lattice *L) {
+    if (L->p.u_osc != 0.0) set_wall_constants(L, L->step);
     StepArgs a{};
     a.g = L->geo;
     a.ph = L->ph;
@@ -678,6 +693,9 @@ static lb_status validate(const lb_params *p) {
     if (p->ybc != LB_YBC_WALLS && p->ybc != LB_YBC_PERIODIC) return fail(LB_EINVAL, "bad ybc");
     if (p->tau_mode != LB_TAU_CONST && p->tau_mode != LB_TAU_RHO) return fail(LB_EINVAL, "bad tau mode");
     if (!(p->kn > 0) || !(p->rho_ref > 0)) return fail(LB_EINVAL, "kn and rho_ref must be positive");
+    if (!std::isfinite(p->u_osc) || !std::isfinite(p->omega_osc))
+        return fail(LB_EINVAL, "oscillating wall amplitude and frequency must be finite");
+    if (p->u_osc != 0.0 && p->ybc != LB_YBC_WALLS) return fail(LB_EINVAL, "an oscillating wall needs walls");
     const int tw = p->tile_w > 0 ? p->tile_w : p->nx;
     if (tw != p->nx && tw % 64 != 0) return fail(LB_EINVAL, "tile_w must be a multiple of 64 (or nx)");
     if (p->xbc == LB_XBC_PRESSURE && p->nx < 4) return fail(LB_EINVAL, "pressure boundary needs nx >= 4");
@@ -1634,6 +1652,7 @@ lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stre
         if (L->p.storage != lattices[0]->p.storage) return fail(LB_EINVAL, "lattices of one batch share a storage type");
         if (L->p.iface != LB_IFACE_HERMITE) return fail(LB_EUNSUPPORTED, "batches use the Hermite interface");
         if (L->closure_on) return fail(LB_EUNSUPPORTED, "lattice %d uses the learned closure", l);
+        if (L->p.u_osc != 0.0) return fail(LB_EUNSUPPORTED, "lattice %d has an oscillating wall", l);
         if (L->cur != cur) return fail(LB_ESTATE, "lattices of one batch must be at the same copy parity");
         for (int m = 0; m < l; ++m)
             if (lattices[m] == L) return fail(LB_EINVAL, "lattice %d listed twice", l);

@@ -16,6 +16,13 @@ Workloads (all synthetic: the paper's cases are analytic channel flows):
                = 2, outlet Kn = 0.2 (relaxation time ~ 1/rho), bands per
                64-column tile from the non-equilibrium indicator every 500
                steps, FP32 or BF16 storage.
+  osc_couette  oscillatory Couette flow (Sec. 3.5): nx = 8 (periodic) x
+               ny = 100, bottom plate moving along x with u_w sin(omega t),
+               u_w = 0.05, top plate at rest, Stokes number
+               beta = sqrt(omega H^2 / nu) = 4 with nu = Kn H (the BGK
+               viscosity mu / rho = tau), Kn in {0.0178, 0.1, 0.3}; the
+               low-order set in the middle 70 % (bands of 15 rows at each
+               wall), M-D2Q9-36 and M-D2Q16-36 against all-D2Q36, FP64.
   batch_c5     128 independent channels, nx = 8 (periodic), ny uniform in
                [32, 512], Kn log-spaced in [0.01, 1], near-wall bands of
                8-64 rows (at most a third of the channel), velocity-set
@@ -73,6 +80,9 @@ POISEUILLE_C2 = dict(nx=1024, ny=512, kn=0.05, kn_sweep=(0.01, 0.05, 0.1), n_low
 PRESSURE_C3 = dict(nx=4096, ny=256, kn=0.2, n_low=D2Q9, n_high=D2Q36, eq_low=2, eq_high=4,
                    rho_in=2.0, rho_out=1.0, tile_w=64, theta=0.01, bmin=8, bmax=64, regrid=500,
                    cfl=0.3, storage="f32", steps=20000)
+
+OSC_COUETTE = dict(nx=8, ny=100, kn=0.0178, kn_sweep=(0.0178, 0.1, 0.3), u_osc=0.05, beta=4.0,
+                   bands=(15, 15), pairs=((3, 2, 6, 4), (4, 3, 6, 4)), storage="f64", periods=3)
 
 BATCH_C5 = dict(count=128, nx=8, ny_range=(32, 512), kn_range=(0.01, 1.0), band_range=(8, 64),
                 pairs=((3, 2, 4, 3), (3, 2, 6, 4), (4, 3, 6, 4)), u_wall=0.05, gx=1e-6, storage="f32",
