@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbo.c")
 _LIB = os.path.join(_HERE, "liblbo.so")
 
-CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-shared", "-fPIC", "-std=c11"]
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-std=c11"]
 
 
 def build() -> str:
@@ -79,6 +79,8 @@ def _declare(L):
     L.lbo_bands_from_indicator.argtypes = [C.c_void_p, _dp, C.c_double, C.c_int, C.c_int, _ip, _ip]
     L.lbo_step_count.restype = C.c_long
     L.lbo_step_count.argtypes = [C.c_void_p]
+    L.lbo_set_threads.argtypes = [C.c_int]
+    L.lbo_threads.restype = C.c_int
 
 
 def _d(a):
@@ -164,6 +166,16 @@ def project(ns: int, ords: int, nd: int, ordd: int, fs, closure=None):
 def face_value(nu, fm1, f0, fp1, fp2) -> float:
     """TVD/minmod face value F_{i+1/2} of Sec. 3.1 (mirrored for nu < 0)."""
     return lib().lbo_face_value(nu, fm1, f0, fp1, fp2)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's node loops (OpenMP over rows); results are
+    the same for any count."""
+    lib().lbo_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(lib().lbo_threads())
 
 
 def default_dt(n_high: int, cfl: float = 0.5) -> float:

@@ -299,3 +299,28 @@ def test_region_change_round_trip(oracle):
     reg = L.region()
     m = reg == 0
     np.testing.assert_allclose(f1[:, m], f0[:, m], rtol=0, atol=1e-15)
+
+
+def test_results_do_not_depend_on_thread_count(oracle):
+    # the node loops run over rows on several threads; every node is computed
+    # the same way on any count, so one and several threads agree bit for bit
+    # (coupled sets, pressure columns, walls, a region change, indicator)
+    def run(threads):
+        oracle.set_threads(threads)
+        L = oracle.Lattice(70, 33, kn=0.2, n_low=3, n_high=6, eq_low=2, eq_high=4, xbc=oracle.XBC_PRESSURE,
+                           rho_in=1.2, rho_out=1.0, tau_mode=oracle.TAU_RHO, tile_w=64, dt=0.3 / 3.3242574335521)
+        L.set_regions([5, 7], [6, 4])
+        xx = np.arange(70)[None, :] * np.ones((34, 1))
+        L.init_equilibrium(1.2 - 0.2 * xx / 69, 0 * xx, 0 * xx)
+        L.step(40)
+        B = L.indicator()
+        L.update_regions(*L.bands_from_indicator(B, 1e-4, 3, 12))
+        L.step(20)
+        return [L.get_populations(0), L.get_populations(1), L.indicator(), *L.moments()]
+    n0 = oracle.threads()
+    try:
+        a, b = run(1), run(max(4, n0))
+    finally:
+        oracle.set_threads(n0)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
