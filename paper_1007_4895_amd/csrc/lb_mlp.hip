@@ -3,8 +3,8 @@
 // closure evaluation used by the tests.
 //
 // Training is written as dense layers over a batch, one thread per output
-// element; every reduction over the batch runs in a fixed order inside one
-// thread, so gradients are deterministic.
+// element; every reduction over the batch runs in a fixed order (per-thread
+// strided sums, then a fixed tree in LDS), so gradients are deterministic.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -42,19 +42,31 @@ __global__ void k_dense_back(const float *D, int M, const float *W, const float 
     out[idx] = s * (1.0f - h * h);
 }
 
-// gW[c][k] = sum_r D[r][c] H[r][k], gb[c] = sum_r D[r][c]
-__global__ void k_outer(const float *D, int M, const float *H, int K, int64_t n, float *gW, float *gb) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx < M * K) {
-        const int c = idx / K, k = idx % K;
-        float s = 0.0f;
-        for (int64_t r = 0; r < n; ++r) s += D[r * M + c] * H[r * K + k];
-        gW[idx] = s;
-    } else if (idx < M * K + M) {
-        const int c = idx - M * K;
-        float s = 0.0f;
-        for (int64_t r = 0; r < n; ++r) s += D[r * M + c];
-        gb[c] = s;
+// gW[c][k] = sum_r D[r][c] H[r][k], gb[c] = sum_r D[r][c]: one block per
+// output element (weights first, then biases); thread t sums the rows
+// t, t + 256, ..., and the block adds the 256 partial sums in a fixed
+// tree, so the gradient does not depend on scheduling
+__global__ __launch_bounds__(256) void k_outer(const float *D, int M, const float *H, int K, int64_t n, float *gW,
+                                               float *gb) {
+    __shared__ float sh[256];
+    const int idx = blockIdx.x;
+    const bool bias = idx >= M * K;
+    const int c = bias ? idx - M * K : idx / K, k = bias ? 0 : idx % K;
+    float s = 0.0f;
+    if (bias) {
+        for (int64_t r = threadIdx.x; r < n; r += 256) s += D[r * M + c];
+    } else {
+        for (int64_t r = threadIdx.x; r < n; r += 256) s += D[r * M + c] * H[r * K + k];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (bias) gb[c] = sh[0];
+        else gW[idx] = sh[0];
     }
 }
 
@@ -233,13 +245,13 @@ lb_status lb_mlp_loss_grad(const float *params, const float *x, const float *t, 
     hipLaunchKernelGGL(k_dense, dim3(blocks(n * 64)), dim3(256), 0, s, H1, 64, W2, b2, H2, 64, n, 1);
     hipLaunchKernelGGL(k_dense, dim3(blocks(n * 8)), dim3(256), 0, s, H2, 64, W3, b3, Y, 8, n, 0);
     hipLaunchKernelGGL(k_loss, dim3(blocks(n)), dim3(256), 0, s, Y, t, flag, n, dY, lv);
-    hipLaunchKernelGGL(k_outer, dim3(blocks(8 * 64 + 8)), dim3(256), 0, s, dY, 8, H2, 64, n, grad + MLP_OFF_W3,
+    hipLaunchKernelGGL(k_outer, dim3(8 * 64 + 8), dim3(256), 0, s, dY, 8, H2, 64, n, grad + MLP_OFF_W3,
                        grad + MLP_OFF_B3);
     hipLaunchKernelGGL(k_dense_back, dim3(blocks(n * 64)), dim3(256), 0, s, dY, 8, W3, H2, dZ2, 64, n);
-    hipLaunchKernelGGL(k_outer, dim3(blocks(64 * 64 + 64)), dim3(256), 0, s, dZ2, 64, H1, 64, n, grad + MLP_OFF_W2,
+    hipLaunchKernelGGL(k_outer, dim3(64 * 64 + 64), dim3(256), 0, s, dZ2, 64, H1, 64, n, grad + MLP_OFF_W2,
                        grad + MLP_OFF_B2);
     hipLaunchKernelGGL(k_dense_back, dim3(blocks(n * 64)), dim3(256), 0, s, dZ2, 64, W2, H1, dZ1, 64, n);
-    hipLaunchKernelGGL(k_outer, dim3(blocks(64 * 10 + 64)), dim3(256), 0, s, dZ1, 64, x, 10, n, grad,
+    hipLaunchKernelGGL(k_outer, dim3(64 * 10 + 64), dim3(256), 0, s, dZ1, 64, x, 10, n, grad,
                        grad + MLP_OFF_B1);
     hipLaunchKernelGGL(k_mean1, dim3(1), dim3(256), 0, s, lv, n, loss);
     return hipGetLastError() == hipSuccess ? LB_OK : lb_internal_fail(LB_EDEVICE, "mlp gradient launch failed");

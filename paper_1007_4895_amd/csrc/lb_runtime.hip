@@ -193,8 +193,22 @@ void wall_constants(int n, int eq, const double *x, const double *w, const doubl
 }
 
 // ------------------------------------------------ generic (untemplated) kernels
-__global__ void k_sum3_partial(const double *a, const double *b, const double *c, int64_t n, double *part) {
-    __shared__ double sh[3][256];
+// Sum over the 64 lanes of a wave by a fixed butterfly (xor 32, 16, ..., 1):
+// every lane ends with the same, order-independent-of-scheduling total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// Sums of three per-node FP64 fields (rho, rho ux, rho uy): each thread
+// accumulates a fixed strided subset, each wave reduces its lanes by a
+// butterfly, and wave 0 adds the four wave totals in order; one partial
+// per block.  The order never depends on timing, so the sums are
+// deterministic.
+__global__ __launch_bounds__(256) void k_sum3_partial(const double *a, const double *b, const double *c, int64_t n,
+                                                      double *part) {
+    __shared__ double sh[3][4];
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
         double r = a[k];
@@ -202,26 +216,36 @@ __global__ void k_sum3_partial(const double *a, const double *b, const double *c
         s1 += r * b[k];
         s2 += r * c[k];
     }
-    sh[0][threadIdx.x] = s0;
-    sh[1][threadIdx.x] = s1;
-    sh[2][threadIdx.x] = s2;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
-        __syncthreads();
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = s0;
+        sh[1][w] = s1;
+        sh[2][w] = s2;
     }
-    if (threadIdx.x == 0)
-        for (int q = 0; q < 3; ++q) part[q * 1024 + blockIdx.x] = sh[q][0];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int q = threadIdx.x;
+        part[q * 1024 + blockIdx.x] = ((sh[q][0] + sh[q][1]) + sh[q][2]) + sh[q][3];
+    }
 }
 
-__global__ void k_sum3_final(double *part, int nb) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        for (int q = 0; q < 3; ++q) {
-            double s = 0.0;
-            for (int b = 0; b < nb; ++b) s += part[q * 1024 + b];
-            part[q * 1024] = s;
-        }
+// Final sums of the nb <= 1024 block partials, the same way (one block).
+__global__ __launch_bounds__(256) void k_sum3_final(double *part, int nb) {
+    __shared__ double sh[3][4];
+    const int w = threadIdx.x >> 6;
+    for (int q = 0; q < 3; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 256) s += part[q * 1024 + b];
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) sh[q][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int q = threadIdx.x;
+        part[q * 1024] = ((sh[q][0] + sh[q][1]) + sh[q][2]) + sh[q][3];
     }
 }
 
@@ -1065,7 +1089,7 @@ lb_status lb_conservation(lb_lattice *L, double out[3]) {
     const int nb = int(std::min<size_t>(1024, (N + 255) / 256));
     hipLaunchKernelGGL(k_sum3_partial, dim3(nb), dim3(256), 0, L->stream, L->d_mom, L->d_mom + N, L->d_mom + 2 * N,
                        int64_t(N), L->d_part);
-    hipLaunchKernelGGL(k_sum3_final, dim3(1), dim3(64), 0, L->stream, L->d_part, nb);
+    hipLaunchKernelGGL(k_sum3_final, dim3(1), dim3(256), 0, L->stream, L->d_part, nb);
     HIPCHK(hipGetLastError());
     double h[3];
     for (int q = 0; q < 3; ++q)
