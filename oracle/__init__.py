@@ -187,7 +187,7 @@ def default_dt(n_high: int, cfl: float = 0.5) -> float:
 # ------------------------------------------------------------------- lattice
 TAU_CONST, TAU_RHO = 0, 1
 XBC_PERIODIC, XBC_PRESSURE = 0, 1
-YBC_WALLS, YBC_PERIODIC = 0, 1
+YBC_WALLS, YBC_PERIODIC, YBC_SHEAR = 0, 1, 2
 IFACE_HERMITE, IFACE_PAPER = 0, 1
 REG_LOW, REG_HIGH, REG_IFACE = 0, 1, 2
 
@@ -197,13 +197,15 @@ class Lattice:
     each wall per column tile, rows 0..ny.  Populations are [Q][ny+1][nx].
     u_osc, omega_osc: the bottom wall also moves along x with
     u_osc sin(omega_osc t), t the time of the level being computed
-    (oscillatory Couette flow, Sec. 3.5)."""
+    (oscillatory Couette flow, Sec. 3.5).  ybc=YBC_SHEAR: a wall at the
+    bottom and an imposed shear rate `shear` above the top row (Kramers'
+    problem, Sec. 3.3)."""
 
     def __init__(self, nx, ny, *, kn, n_low=3, n_high=3, eq_low=2, eq_high=None,
                  force_low=None, force_high=None, dt=None, rho_ref=1.0, tau_mode=TAU_CONST,
                  gx=0.0, gy=0.0, u_wall=((0.0, 0.0), (0.0, 0.0)), xbc=XBC_PERIODIC,
                  ybc=YBC_WALLS, rho_in=1.0, rho_out=1.0, iface=IFACE_HERMITE, tile_w=None,
-                 u_osc=0.0, omega_osc=0.0):
+                 u_osc=0.0, omega_osc=0.0, shear=0.0):
         eq_high = eq_low if eq_high is None else eq_high
         force_low = eq_low if force_low is None else force_low
         force_high = eq_high if force_high is None else force_high
@@ -217,7 +219,7 @@ class Lattice:
         self.tile_w = tile_w
         self.ntiles = (nx + tile_w - 1) // tile_w
         dp = np.array([kn, rho_ref, dt, gx, gy, u_wall[0][0], u_wall[0][1], u_wall[1][0],
-                       u_wall[1][1], rho_in, rho_out, u_osc, omega_osc], dtype=np.float64)
+                       u_wall[1][1], rho_in, rho_out, u_osc, omega_osc, shear], dtype=np.float64)
         ip = np.array([nx, ny, n_low, n_high, eq_low, eq_high, force_low, force_high,
                        tau_mode, xbc, ybc, iface, tile_w], dtype=np.int32)
         self._h = lib().lbo_create(_d(dp), _i(ip))
