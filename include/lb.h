@@ -53,7 +53,12 @@ typedef enum { LB_STORE_F64 = 0, LB_STORE_F32 = 1, LB_STORE_BF16 = 2 } lb_storag
 typedef enum { LB_IFACE_HERMITE = 0, LB_IFACE_PAPER = 1 } lb_iface;
 typedef enum { LB_TAU_CONST = 0, LB_TAU_RHO = 1 } lb_tau_mode;
 typedef enum { LB_XBC_PERIODIC = 0, LB_XBC_PRESSURE = 1 } lb_xbc;
-typedef enum { LB_YBC_WALLS = 0, LB_YBC_PERIODIC = 1 } lb_ybc;
+/* LB_YBC_SHEAR (Kramers' problem, Sec. 3.3): a diffuse wall on row 0 and,
+ * above the top row ny (an ordinary gas node), the far-field condition of
+ * an imposed shear rate: ghost row k = 1, 2 holds the equilibrium at the top
+ * node's density with its velocity raised by shear_top * k along x, plus the
+ * top node's non-equilibrium part. */
+typedef enum { LB_YBC_WALLS = 0, LB_YBC_PERIODIC = 1, LB_YBC_SHEAR = 2 } lb_ybc;
 
 typedef struct lb_params {
     int32_t nx, ny;            /* nx columns (>= 2); ny intervals -> ny+1 rows (>= 4) */
@@ -76,6 +81,7 @@ typedef struct lb_params {
                                   Sec. 3.5): its x velocity is u_wall[0] +
                                   u_osc sin(omega_osc t), with t = (n + 1) dt when
                                   step n -> n + 1 applies the wall condition */
+    double shear_top;          /* LB_YBC_SHEAR: imposed du/dy above the top row */
 } lb_params;
 
 typedef struct lb_lattice lb_lattice;

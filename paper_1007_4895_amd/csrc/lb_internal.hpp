@@ -16,7 +16,8 @@
 namespace lbi {
 
 enum : int32_t { XBC_PERIODIC = 0, XBC_PRESSURE = 1 };
-enum : int32_t { YBC_WALLS = 0, YBC_PERIODIC = 1 };
+// YBC_SHEAR: a wall at the bottom, an imposed shear rate above the top row
+enum : int32_t { YBC_WALLS = 0, YBC_PERIODIC = 1, YBC_SHEAR = 2 };
 enum : int32_t { IF_HERMITE = 0, IF_PAPER = 1 };
 enum : int32_t { TAU_CONST = 0, TAU_RHO = 1 };
 enum : int32_t { REG_LOW = 0, REG_HIGH = 1, REG_IFACE = 2 };
@@ -44,6 +45,7 @@ struct Phys {
     double kn;         // Kn at rho_ref
     int32_t tau_mode;
     int32_t pad;
+    double shear;      // YBC_SHEAR: velocity gradient du/dy imposed above the top row
 };
 
 // Per-set kernel constants, in double and float: nu_p = x_p dt and

@@ -454,6 +454,25 @@ __device__ void emit_node(const Buf &b, int copy, int i, int j, double shift, co
             store_node_d<ST, SS>(b, copy, i, g.ny + 1, shift, f);
             store_node_d<ST, SS>(b, copy, i, g.ny + 2, shift, f);
         }
+    } else if (g.ybc == YBC_SHEAR) {
+        if (j == 0) {
+            store_node_d<ST, SS>(b, copy, i, -1, shift, f);
+            store_node_d<ST, SS>(b, copy, i, -2, shift, f);
+        }
+        if (j == g.ny) {
+            // imposed shear (Kramers' problem, Sec. 3.3): equilibrium at the
+            // node's density with its velocity raised by shear * k, plus the
+            // node's non-equilibrium part
+            double rho, ux, uy, en[SS::Q], eg[SS::Q], gq[SS::Q];
+            moments_d<SS>(f, rho, ux, uy);
+            feq_d<SS>(rho, ux, uy, en);
+            for (int k = 1; k <= 2; ++k) {
+                feq_d<SS>(rho, ux + ph.shear * double(k), uy, eg);
+#pragma unroll
+                for (int a = 0; a < SS::Q; ++a) gq[a] = eg[a] + (f[a] - en[a]);
+                store_node_d<ST, SS>(b, copy, i, g.ny + k, shift, gq);
+            }
+        }
     } else {
         if (j < 2) store_node_d<ST, SS>(b, copy, i, j + g.nrow, shift, f);
         if (j >= g.nrow - 2) store_node_d<ST, SS>(b, copy, i, j - g.nrow, shift, f);
@@ -873,7 +892,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
         // wall rows: uniform for a wide item; per lane group for a narrow
         // one, whose wall code runs when any lane has a wall row and only
         // stores from those lanes
-        const bool wall_l = g.ybc == YBC_WALLS && (j == 0 || j == g.ny) && (!NW || j < jl1);
+        const bool wall_l = (j == 0 ? g.ybc != YBC_PERIODIC : (j == g.ny && g.ybc == YBC_WALLS)) && (!NW || j < jl1);
         const bool wall = NW ? __builtin_amdgcn_ballot_w64(wall_l) != 0 : wall_l;
         const unsigned vw = NW ? (wall_l ? vs : OOB) : vs;
         const bool bottom = j == 0;
@@ -1213,6 +1232,13 @@ __device__ void emit_pop(const Buf &b, int copy, int i, int j, double shift, int
     if (g.ybc == YBC_WALLS) {
         if (j == 0) { put(i, -1, sv); put(i, -2, sv); }
         if (j == g.ny) { put(i, g.ny + 1, sv); put(i, g.ny + 2, sv); }
+    } else if (g.ybc == YBC_SHEAR) {
+        if (j == 0) { put(i, -1, sv); put(i, -2, sv); }
+        if (j == g.ny) {
+            const double neq = v - feq_one<SS>(rho, ux, uy, t);
+            put(i, g.ny + 1, feq_one<SS>(rho, ux + ph.shear, uy, t) + neq - w_of<SS>(t) * shift);
+            put(i, g.ny + 2, feq_one<SS>(rho, ux + 2.0 * ph.shear, uy, t) + neq - w_of<SS>(t) * shift);
+        }
     } else {
         if (j < 2) put(i, j + g.nrow, sv);
         if (j >= g.nrow - 2) put(i, j - g.nrow, sv);

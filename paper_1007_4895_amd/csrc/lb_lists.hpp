@@ -106,8 +106,9 @@ inline int build_lists(const Decomp &D, std::vector<int32_t> &fin, std::vector<i
     nproj[0] = int(proj.size() / 2);
     nproj[1] = int(ph.size() / 2);
     proj.insert(proj.end(), ph.begin(), ph.end());
-    // row images (periodic y: the first and last two rows) and pressure
-    // columns (the first and last column), row-major
+    // row images (periodic y: the first and last two rows), imposed-shear
+    // ghost rows (the top row) and pressure columns (the first and last
+    // column), row-major
     auto add_fin = [&](int i, int j) {
         const int r = reg(i, j);
         if (r == REG_IFACE) return;
@@ -118,6 +119,9 @@ inline int build_lists(const Decomp &D, std::vector<int32_t> &fin, std::vector<i
     };
     for (int j = 0; j < nrow; ++j) {
         if (per_y && (j < 2 || j >= nrow - 2)) {
+            for (int i = 0; i < nx; ++i) add_fin(i, j);
+        } else if (D.ybc == YBC_SHEAR && j == nrow - 1) {
+            // the imposed-shear ghost rows above the top row
             for (int i = 0; i < nx; ++i) add_fin(i, j);
         } else if (press) {
             add_fin(0, j);

@@ -714,12 +714,14 @@ static lb_status validate(const lb_params *p) {
     if (p->storage < 0 || p->storage > 2) return fail(LB_EINVAL, "bad storage");
     if (p->iface != LB_IFACE_HERMITE && p->iface != LB_IFACE_PAPER) return fail(LB_EINVAL, "bad interface");
     if (p->xbc != LB_XBC_PERIODIC && p->xbc != LB_XBC_PRESSURE) return fail(LB_EINVAL, "bad xbc");
-    if (p->ybc != LB_YBC_WALLS && p->ybc != LB_YBC_PERIODIC) return fail(LB_EINVAL, "bad ybc");
+    if (p->ybc != LB_YBC_WALLS && p->ybc != LB_YBC_PERIODIC && p->ybc != LB_YBC_SHEAR)
+        return fail(LB_EINVAL, "bad ybc");
+    if (!std::isfinite(p->shear_top)) return fail(LB_EINVAL, "shear rate must be finite");
     if (p->tau_mode != LB_TAU_CONST && p->tau_mode != LB_TAU_RHO) return fail(LB_EINVAL, "bad tau mode");
     if (!(p->kn > 0) || !(p->rho_ref > 0)) return fail(LB_EINVAL, "kn and rho_ref must be positive");
     if (!std::isfinite(p->u_osc) || !std::isfinite(p->omega_osc))
         return fail(LB_EINVAL, "oscillating wall amplitude and frequency must be finite");
-    if (p->u_osc != 0.0 && p->ybc != LB_YBC_WALLS) return fail(LB_EINVAL, "an oscillating wall needs walls");
+    if (p->u_osc != 0.0 && p->ybc == LB_YBC_PERIODIC) return fail(LB_EINVAL, "an oscillating wall needs walls");
     const int tw = p->tile_w > 0 ? p->tile_w : p->nx;
     if (tw != p->nx && tw % 64 != 0) return fail(LB_EINVAL, "tile_w must be a multiple of 64 (or nx)");
     if (p->xbc == LB_XBC_PRESSURE && p->nx < 4) return fail(LB_EINVAL, "pressure boundary needs nx >= 4");
@@ -805,6 +807,7 @@ lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t byte
     L->ph.gx = p->gx;
     L->ph.gy = p->gy;
     for (int k = 0; k < 4; ++k) L->ph.uw[k] = p->u_wall[k];
+    L->ph.shear = p->ybc == LB_YBC_SHEAR ? p->shear_top : 0.0;
     L->ph.tau_mode = p->tau_mode;
     L->ph.kn = p->kn;
     L->d_blo = reinterpret_cast<int32_t *>(L->ws + lay.off_blo);

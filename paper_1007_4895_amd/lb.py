@@ -20,7 +20,7 @@ STORE_F64, STORE_F32, STORE_BF16 = 0, 1, 2
 IFACE_HERMITE, IFACE_PAPER = 0, 1
 TAU_CONST, TAU_RHO = 0, 1
 XBC_PERIODIC, XBC_PRESSURE = 0, 1
-YBC_WALLS, YBC_PERIODIC = 0, 1
+YBC_WALLS, YBC_PERIODIC, YBC_SHEAR = 0, 1, 2
 
 STORAGE = {"f64": STORE_F64, "f32": STORE_F32, "bf16": STORE_BF16}
 
@@ -42,7 +42,7 @@ class Params(C.Structure):
         ("kn", C.c_double), ("rho_ref", C.c_double), ("cfl", C.c_double), ("dt", C.c_double),
         ("gx", C.c_double), ("gy", C.c_double), ("u_wall", C.c_double * 4),
         ("rho_in", C.c_double), ("rho_out", C.c_double),
-        ("u_osc", C.c_double), ("omega_osc", C.c_double),
+        ("u_osc", C.c_double), ("omega_osc", C.c_double), ("shear_top", C.c_double),
     ]
 
 
@@ -135,7 +135,7 @@ def make_params(nx, ny, *, kn, n_low=3, n_high=3, eq_low=2, eq_high=None, storag
                 iface=IFACE_HERMITE, tau_mode=TAU_CONST, xbc=XBC_PERIODIC, ybc=YBC_WALLS,
                 tile_w=0, rho_ref=1.0, cfl=0.5, dt=0.0, gx=0.0, gy=0.0,
                 u_wall=((0.0, 0.0), (0.0, 0.0)), rho_in=1.0, rho_out=1.0, u_osc=0.0,
-                omega_osc=0.0) -> Params:
+                omega_osc=0.0, shear_top=0.0) -> Params:
     p = Params()
     _check(lib().lb_params_default(C.byref(p)))
     p.nx, p.ny = nx, ny
@@ -151,6 +151,7 @@ def make_params(nx, ny, *, kn, n_low=3, n_high=3, eq_low=2, eq_high=None, storag
         p.u_wall[k] = v
     p.rho_in, p.rho_out = rho_in, rho_out
     p.u_osc, p.omega_osc = u_osc, omega_osc
+    p.shear_top = shear_top
     return p
 
 

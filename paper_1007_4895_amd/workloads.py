@@ -23,6 +23,12 @@ Workloads (all synthetic: the paper's cases are analytic channel flows):
                viscosity mu / rho = tau), Kn in {0.0178, 0.1, 0.3}; the
                low-order set in the middle 70 % (bands of 15 rows at each
                wall), M-D2Q9-36 and M-D2Q16-36 against all-D2Q36, FP64.
+  kramers      Kramers' problem (Sec. 3.3): nx = 8 (periodic), a plate at
+               rest on row 0 and a shear rate s = 1e-4 imposed above row
+               ny = 400 = 200 mean free paths (lambda = tau = 2 nodes,
+               Kn = 0.005 of the 400-node height), D2Q36 within 10 lambda
+               of the plate (20 rows), D2Q9 beyond; started from the
+               far-field shear flow, FP64.
   batch_c5     128 independent channels, nx = 8 (periodic), ny uniform in
                [32, 512], Kn log-spaced in [0.01, 1], near-wall bands of
                8-64 rows (at most a third of the channel), velocity-set
@@ -83,6 +89,8 @@ PRESSURE_C3 = dict(nx=4096, ny=256, kn=0.2, n_low=D2Q9, n_high=D2Q36, eq_low=2, 
 
 OSC_COUETTE = dict(nx=8, ny=100, kn=0.0178, kn_sweep=(0.0178, 0.1, 0.3), u_osc=0.05, beta=4.0,
                    bands=(15, 15), pairs=((3, 2, 6, 4), (4, 3, 6, 4)), storage="f64", periods=3)
+
+KRAMERS = dict(nx=8, ny=400, kn=0.005, shear=1e-4, band=20, storage="f64")
 
 BATCH_C5 = dict(count=128, nx=8, ny_range=(32, 512), kn_range=(0.01, 1.0), band_range=(8, 64),
                 pairs=((3, 2, 4, 3), (3, 2, 6, 4), (4, 3, 6, 4)), u_wall=0.05, gx=1e-6, storage="f32",
