@@ -313,6 +313,8 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="run only the 128-channel batch section (profiling)")
     ap.add_argument("--no-large", action="store_true", help="skip the 4096-column (beyond the Infinity Cache) section")
     ap.add_argument("--no-c3", action="store_true", help="skip the pressure-channel (regrid) section")
+    ap.add_argument("--no-closure", action="store_true", help="skip the learned-closure (C4) section")
+    ap.add_argument("--closure-only", action="store_true", help="run only the learned-closure section")
     ap.add_argument("--c3-only", action="store_true", help="run only the pressure-channel section (profiling)")
     ap.add_argument("--large-only", action="store_true", help="run only the 4096-column section (profiling)")
     ap.add_argument("--profile-steps", type=int, default=2000,
@@ -340,6 +342,10 @@ def main():
         return
     if args.c3_only:
         print(json.dumps({"pressure_c3": c3_section(lb, W, torch)}))
+        return
+    if args.closure_only:
+        from paper_1007_4895_amd import closure
+        print(json.dumps({"closure_c4": closure.report()}))
         return
     if args.large_only:
         print(json.dumps({"c2_wide_4096": large_section(lb, W, torch, 2000)}))
@@ -492,6 +498,14 @@ def main():
     if not args.no_c3:
         out["pressure_c3"] = c3_section(lb, W, torch)
         print(f"c3: {out['pressure_c3']}", flush=True)
+
+    # ------------ learned closure (C4): training, and what it changes in the flow
+    if not args.no_closure:
+        from paper_1007_4895_amd import closure
+        t0 = time.perf_counter()
+        out["closure_c4"] = closure.report()
+        out["closure_c4"]["section_s"] = round(time.perf_counter() - t0, 1)
+        print(f"closure: {out['closure_c4']}", flush=True)
 
     # ------------------- 128 independent channels: one batch vs one launch per case
     if not args.no_batch:

@@ -297,6 +297,15 @@ lb_status lb_closure_samples(lb_lattice *L, const int32_t *nodes, int64_t n, dou
  * it.  params == NULL restores the analytic projection.  Waits. */
 lb_status lb_set_closure(lb_lattice *L, const float *params, const float *norm);
 
+/* Use the network's region flag (its two last outputs: does the node call
+ * for the high-order set) in lb_update_regions, beside the indicator: every
+ * node whose flag logits favour the high set counts as above the threshold
+ * in the band rule.  Inputs are the node's D2Q9 populations, or its D2Q36
+ * populations restricted to D2Q9 (Hermite projection).  Needs
+ * lb_set_closure first (LB_ESTATE otherwise); lb_set_closure(NULL) turns it
+ * off. */
+lb_status lb_set_closure_flags(lb_lattice *L, int32_t enable);
+
 /* ---------------------------------------------------------------------
  * Batches: many independent lattices (channels of different size, Kn and
  * velocity-set pair) advanced together.  Each step issues, in order on the

@@ -196,12 +196,14 @@ def velocity_error(L, ref):
 
 
 def report(nx=4096, ny=256, runs=8, steps=20000, snaps=16, per_snap=16384, train_steps=4000, kn_eval=0.2,
-           bands=(16, 16), seed=40):
+           bands=(16, 16), seed=40, theta=0.01, regrid_every=500):
     """The learned closure on the pressure-driven channel: data from
     all-D2Q36 runs (Kn log-uniform in [0.02, 0.5]), training on the GPU,
     held-out sample and lift errors at kn_eval, and the coupled channel's
     velocity error against all-D2Q36 with the analytic and the learned lift
-    (fixed bands).  Returns a dict."""
+    (fixed bands), and with bands from the indicator every regrid_every
+    steps (analytic lift, learned lift, learned lift with the network's
+    region flag beside the indicator).  Returns a dict."""
     import time
 
     import torch
@@ -248,6 +250,31 @@ def report(nx=4096, ny=256, runs=8, steps=20000, snaps=16, per_snap=16384, train
                       "mlups": round(nx * (ny + 1) * (steps - 200) / sec / 1e6, 1)}
         L.close()
     out["coupled_vs_all_d2q36"] = {"kn_outlet": kn_eval, "bands": list(bands), **flow}
+    # bands from the indicator every `regrid` steps: the analytic lift, and
+    # the learned lift with the network's region flag beside the indicator
+    regrid = {}
+    for name, use, flags in (("analytic", False, False), ("learned", True, False), ("learned_flags", True, True)):
+        L = channel(nx, ny, kn_eval, storage="f32", all_high=False, bands=(8, 8))
+        if use:
+            L.set_closure(params, norm)
+            L.set_closure_flags(flags)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        done, mb = 0, []
+        while done < steps:
+            L.step(min(regrid_every, steps - done))
+            done += regrid_every
+            if done < steps:
+                L.update_regions(theta, 8, 64)
+                lo, hi = L.get_regions()
+                mb.append(float(np.mean(np.concatenate([lo, hi]))))
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        regrid[name] = {"e_model": velocity_error(L, ref), "mlups": round(nx * (ny + 1) * steps / sec / 1e6, 1),
+                        "mean_band_rows": round(float(np.mean(mb)), 1) if mb else 8.0}
+        L.close()
+    out["regrid_vs_all_d2q36"] = {"kn_outlet": kn_eval, "theta": theta, "every": regrid_every, "bands": [8, 64],
+                                  **regrid}
     return out
 
 

@@ -28,6 +28,9 @@ struct Inst {
     static void closure_infer(const StepArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_closure_infer<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
     }
+    static void closure_flags(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_closure_flags<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
+    }
     static void closure_samples(const NodeArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_closure_samples<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
     }
@@ -97,6 +100,7 @@ struct Inst {
         k.project = &project;
         k.closure_infer = &closure_infer;
         k.closure_samples = &closure_samples;
+        k.closure_flags = &closure_flags;
         k.update_pair = update_split<S>() == 1 ? &update_pair : nullptr;
         k.pair_split = pair_split<O>();
         k.finish_batch = &finish_batch;

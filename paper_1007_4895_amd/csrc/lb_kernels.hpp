@@ -1528,8 +1528,10 @@ __device__ __forceinline__ void bf16_split(float v, short &hi, short &lo) {
 
 // xs: standardised inputs of the 16 nodes (K padded to 16 with zeros);
 // hs: LDS scratch [16][64 + 4]; out: c6 of the 16 nodes (rho * (mean + std y))
+// and, when zf is given, the two region-flag logits of each node
 __device__ __forceinline__ void closure_mfma16(const uint16_t *w, const ClosureNorm &cn, const float (*xs)[16],
-                                               float (*hs)[MLP_NH + 4], const float *rs, float (*c6)[6]) {
+                                               float (*hs)[MLP_NH + 4], const float *rs, float (*c6)[6],
+                                               float (*zf)[2] = nullptr) {
     const int l = threadIdx.x & 63;
     const int r = l & 15, kq = l >> 4;
     const f32x4_t zero = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -1605,6 +1607,10 @@ __device__ __forceinline__ void closure_mfma16(const uint16_t *w, const ClosureN
                 const int n = 4 * kq + v;
                 c6[n][r] = rs[n] * (cn.tmean[r] + cn.tstd[r] * (acc[0][v] + b3));
             }
+        } else if (r < MLP_NOUT && zf) {
+            const float b3 = bf16_to_f(w[MLP_OFF_B3 + r]);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) zf[4 * kq + v][r - 6] = acc[0][v] + b3;
         }
     }
     __syncthreads();
@@ -1656,6 +1662,49 @@ __global__ __launch_bounds__(64) void k_closure_infer(const StepArgs A) {
         __syncthreads();
         closure_mfma16(A.clw, A.cn, xs, hs, rs, c6);
         for (int q = lane; q < 6 * nn; q += 64) A.clo[6 * e0 + q] = c6[q / 6][q % 6];
+    }
+}
+
+// The network's region flag of every node, beside the indicator: a node
+// whose flag logits favour the high-order set (z1 > z0) gets an indicator of
+// +infinity in B, so the band rule keeps it in the high set whatever the
+// threshold.  Inputs come from the node's D2Q9 populations, or from its
+// D2Q36 populations restricted to D2Q9 (Hermite projection) in the high
+// bands; one wave per 16 nodes, row-major.  self = low set, other = high.
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(64) void k_closure_flags(const NodeArgs A) {
+    if constexpr (LS::N == 3 && HS::N == 6) {
+        __shared__ float xs[16][16];
+        __shared__ float hs[16][MLP_NH + 4];
+        __shared__ float rs[16];
+        __shared__ float c6[16][6];
+        __shared__ float zf[16][2];
+        const int lane = threadIdx.x;
+        const int64_t nodes = int64_t(A.g.nx) * A.g.nrow;
+        const int64_t e0 = int64_t(blockIdx.x) * 16;
+        const int nn = int(min(int64_t(16), nodes - e0));
+        if (lane < 16) {
+            if (lane < nn) {
+                const int64_t e = e0 + lane;
+                const int j = int(e / A.g.nx), i = int(e - int64_t(j) * A.g.nx);
+                double f9[9];
+                if (region_at(i, j, A.g) == REG_HIGH) {
+                    double f36[36];
+                    load_node_d<ST, HS>(A.other, A.cur, i, j, A.rho_shift, f36);
+                    project_d<HS, LS>(f36, f9, nullptr);
+                } else {
+                    load_node_d<ST, LS>(A.self, A.cur, i, j, A.rho_shift, f9);
+                }
+                closure_inputs<LS>(A.cn, f9, A.ph.rho_ref, xs[lane], rs[lane]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) xs[lane][k] = 0.0f;
+                rs[lane] = 0.0f;
+            }
+        }
+        __syncthreads();
+        closure_mfma16(A.clw, A.cn, xs, hs, rs, c6, zf);
+        if (lane < nn && zf[lane][1] > zf[lane][0]) A.out0[e0 + lane] = __builtin_huge_val();
     }
 }
 

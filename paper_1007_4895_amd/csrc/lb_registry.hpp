@@ -35,6 +35,7 @@ struct KernelSet {
     ProjFn project;        // FP64 projection self -> partner
     StepFn closure_infer;   // learned-closure inference of the lifted nodes (self = low set)
     NodeFn closure_samples; // training samples from an all-high run (self = high set)
+    NodeFn closure_flags;   // the network's region flag into an indicator array (self = low set)
     PairFn update_pair;     // NULL unless the low set is D2Q9
     int pair_split;         // waves per block of update_pair (the high set's split)
     BatchFn finish_batch;   // batched forms (self = low set)

@@ -311,6 +311,7 @@ struct lb_lattice {
     std::vector<int> ev_kind;   // per event pair: 1 = dominant update kernel, 0 = other update
     int64_t count[3];           // nodes per region: low, high, interface rows
     bool closure_on;            // learned closure in the lift
+    bool closure_flags;         // the network's region flag in lb_update_regions
     uint16_t *d_clw;            // closure weights (bf16)
     float *d_clo;               // closure coefficients of the lifted nodes
     ClosureNorm cn;
@@ -1241,6 +1242,16 @@ lb_status lb_update_regions(lb_lattice *L, double theta, int32_t bmin, int32_t b
     if (bmin < 0 || bmax < bmin || bmax > L->p.ny / 2) return fail(LB_EINVAL, "bad band limits");
     lb_status st = lb_indicator(L, L->d_mom, 1);
     if (st != LB_OK) return st;
+    if (L->closure_on && L->closure_flags) {
+        // nodes the network flags count as above any threshold
+        NodeArgs a = node_args(L, 0, L->cur);
+        a.out0 = L->d_mom;
+        a.clw = L->d_clw;
+        a.cn = L->cn;
+        const int64_t nodes = int64_t(L->p.nx) * (L->p.ny + 1);
+        L->ks[0]->closure_flags(a, int((nodes + 15) / 16), L->stream);
+        HIPCHK(hipGetLastError());
+    }
     int32_t *nlo = L->d_oblo, *nhi = L->d_obhi;   // scratch for the new bands
     hipLaunchKernelGGL(k_bands, dim3(L->ntiles), dim3(256), 0, L->stream, L->d_mom, L->geo, theta, bmin, bmax, nlo,
                        nhi);
@@ -1266,6 +1277,7 @@ lb_status lb_set_closure(lb_lattice *L, const float *params, const float *norm) 
     if (!L) return fail(LB_EINVAL, "null lattice");
     if (!params) {
         L->closure_on = false;
+        L->closure_flags = false;
         return LB_OK;
     }
     if (!norm) return fail(LB_EINVAL, "closure needs its standardisation constants");
@@ -1302,6 +1314,13 @@ lb_status lb_closure_samples(lb_lattice *L, const int32_t *nodes, int64_t n, dou
     a.flag = flag;
     if (n) L->ks[1]->closure_samples(a, int((n + 63) / 64), L->stream);
     HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_set_closure_flags(lb_lattice *L, int32_t enable) {
+    if (!L) return fail(LB_EINVAL, "null lattice");
+    if (enable && !L->closure_on) return fail(LB_ESTATE, "set the learned closure first (lb_set_closure)");
+    L->closure_flags = enable != 0;
     return LB_OK;
 }
 

@@ -102,6 +102,7 @@ def lib():
                                           C.c_int64, _vp, _vp]),
             "lb_closure_samples": (C.c_int, [_vp, _vp, C.c_int64, C.c_double, _vp, _vp, _vp]),
             "lb_set_closure": (C.c_int, [_vp, _vp, C.POINTER(C.c_float)]),
+            "lb_set_closure_flags": (C.c_int, [_vp, C.c_int32]),
             "lb_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int32, _vp, C.POINTER(_vp)]),
             "lb_batch_destroy": (None, [_vp]),
             "lb_batch_set_graph": (C.c_int, [_vp, C.c_int32]),
@@ -325,6 +326,11 @@ class Lattice:
             return
         nm = _norm(norm)
         _check(lib().lb_set_closure(self._h, _vp(params.data_ptr()), nm.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def set_closure_flags(self, on=True):
+        """Count the nodes the network flags as above the threshold in
+        update_regions (needs set_closure first)."""
+        _check(lib().lb_set_closure_flags(self._h, 1 if on else 0))
 
     def closure_samples(self, nodes, theta):
         """Training samples at the listed nodes (device int32 tensor of

@@ -279,3 +279,59 @@ def test_closure_training_gain(oracle, lb):
     assert hist[-1][1] < 0.5 * hist[0][1]
     assert e_h < 0.5
     assert ll < 0.8 * la
+
+
+def test_update_regions_with_network_flags(oracle, lb, mlp):
+    # the network's region flag counts beside the indicator in the band rule
+    # (lb_set_closure_flags): the oracle evaluates the same network (bf16
+    # weights, FP64 arithmetic) on its own state, flags the nodes whose
+    # logits favour the high set, and applies its band rule to
+    # "indicator above theta or flagged"
+    import torch  # noqa: F401
+    nx, ny, kn = 256, 48, 0.2
+    G, O = _pressure_pair(oracle, lb, nx, ny, kn, "f64", (8, 8))
+    G.step(300)
+    O.step(300)
+    p, _, _, _ = _net(mlp, 17, 1)
+    norm = _trial_norm()
+    G.set_closure(_dev(p), norm)
+    G.set_closure_flags(True)
+    B = O.indicator()
+    f9, f36, reg = O.get_populations(0), O.get_populations(1), O.region()
+    n = norm.astype(np.float64)
+    X = np.zeros((ny + 1, nx, 10))
+    for j in range(ny + 1):
+        for i in range(nx):
+            f = oracle.project(6, 4, 3, 2, f36[:, j, i]) if reg[j, i] == oracle.REG_HIGH else f9[:, j, i]
+            X[j, i] = mlp.features(oracle, f, kn / float(np.sum(f)))
+    y, _ = mlp.forward(bf16_round(p).astype(np.float64), ((X - n[0:10]) / n[10:20]).reshape(-1, 10))
+    dz = (y[:, 7] - y[:, 6]).reshape(ny + 1, nx)
+    # theta halfway into the widest gap between sorted indicator values
+    # around their 95th percentile (rounding cannot move a node across it)
+    sb = np.sort(B.ravel())
+    k0 = int(0.95 * sb.size)
+    k = k0 - 50 + int(np.argmax(np.diff(sb[k0 - 50:k0 + 50])))
+    theta = 0.5 * (sb[k] + sb[k + 1])
+    # nodes whose logit gap is within rounding of the GPU's bf16 / FP32
+    # evaluation may go either way: tiles whose bands depend on them are
+    # not compared
+    sure_on, maybe_on = dz > 1e-3, dz > -1e-3
+    want = [O.bands_from_indicator(np.where(fl, np.inf, B), theta, 8, 20) for fl in (sure_on, maybe_on)]
+    base = O.bands_from_indicator(B, theta, 8, 20)
+    G.update_regions(theta, 8, 20)
+    got = G.get_regions()
+    checked = 0
+    for side in (0, 1):
+        for t in range(len(got[side])):
+            if want[0][side][t] == want[1][side][t]:
+                assert got[side][t] == want[0][side][t], (side, t)
+                checked += 1
+    assert checked >= len(got[0])
+    # the flags moved bands that the indicator alone would have left
+    assert np.any(want[0][0] != base[0]) or np.any(want[0][1] != base[1])
+    # switched off, the indicator alone decides again
+    G.set_closure_flags(False)
+    G.update_regions(theta, 8, 20)
+    got = G.get_regions()
+    np.testing.assert_array_equal(got[0], base[0])
+    np.testing.assert_array_equal(got[1], base[1])
