@@ -288,7 +288,19 @@ def batch_section(lb, W, torch):
     torch.cuda.synchronize()
     sec_b = time.perf_counter() - t0
     _, launches, kinds = B.info()
+    # the same batch in persistent launches: one launch per graph segment,
+    # each workgroup owning whole channels and looping over the steps
+    B.set_persistent(True)
+    strips_p = B.autotune(20)
+    B.set_graph(seg)
+    B.step(seg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(n_b)
+    torch.cuda.synchronize()
+    sec_p = time.perf_counter() - t0
     B.close()
+    mlups_p = nodes * n_b / sec_p / 1e6
     mlups_b = nodes * n_b / sec_b / 1e6
     mlups_pc = nodes * n_pc / sec_pc / 1e6
     gbs = alg * n_b / sec_b / 1e9
@@ -298,7 +310,12 @@ def batch_section(lb, W, torch):
             "speedup": round(mlups_b / mlups_pc, 2), "us_per_step_batch": round(1e6 * sec_b / n_b, 2),
             "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "graph_segment_steps": seg, "first_segment_s": round(t_cap, 3), "launches_per_step": launches,
-            "set_pairs": kinds, "strip_rows": list(strips), "timed_steps": n_b, "per_case_steps": n_pc}
+            "set_pairs": kinds, "strip_rows": list(strips), "timed_steps": n_b, "per_case_steps": n_pc,
+            "persistent": {"mlups": round(mlups_p, 1), "us_per_step": round(1e6 * sec_p / n_b, 2),
+                           "hbm_gbs_algorithmic": round(alg * n_b / sec_p / 1e9, 1),
+                           "hbm_frac": round(alg * n_b / sec_p / 1e9 / HBM_PEAK_GBS, 4),
+                           "launches_per_segment": 1, "strip_rows": list(strips_p),
+                           "speedup_vs_graph_launches": round(mlups_p / mlups_b, 3)}}
 
 
 def main():

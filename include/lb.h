@@ -332,6 +332,21 @@ typedef struct lb_batch lb_batch;
 lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stream, lb_batch **out);
 void lb_batch_destroy(lb_batch *B);
 
+/* Persistent launches (off by default): one kernel launch advances every
+ * lattice by a run of steps (up to 4096 per launch; with a graph segment
+ * set, one launch per segment, captured).  Each workgroup owns whole
+ * lattices, assigned largest-first by populations x nodes, and loops over
+ * the steps with workgroup barriers only (no workgroup waits on another):
+ * in each step its waves take the lattices' update items in turn, one wave
+ * per item holding all of the item's populations, then its threads take the
+ * projection entries.  Results are bit-identical to lb_step.  Lattices that
+ * need a finish pass (periodic rows, pressure columns) or sets outside one
+ * registered (D2Q36, D2Q16, D2Q9) order triple are refused with
+ * LB_EUNSUPPORTED (the batch stays as it was).  Strip heights apply as for
+ * the other launches (0 = 4 rows).  lb_batch_info reports 0 launches per
+ * step in this mode. */
+lb_status lb_batch_set_persistent(lb_batch *B, int32_t enable);
+
 /* Steps per captured graph (0 = direct launches, the default).  Asynchronous
  * otherwise, like lb_step. */
 lb_status lb_batch_set_graph(lb_batch *B, int32_t segment_steps);

@@ -119,7 +119,11 @@ struct MultiInst {
     static void project(const BatchMulti &m, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_project_multi<ST, lbt::VSet<6, E6>, lbt::VSet<4, E4>>), dim3(grid), dim3(128), 0, s, m);
     }
-    static MultiSet make() { return MultiSet{E6, E4, multi_waves(), &update, &project}; }
+    static void persist(const PersistArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_batch_persistent<ST, lbt::VSet<6, E6>, lbt::VSet<4, E4>>), dim3(grid),
+                           dim3(64 * PERSIST_WAVES), 0, s, a);
+    }
+    static MultiSet make() { return MultiSet{E6, E4, multi_waves(), &update, &project, &persist, PERSIST_WAVES}; }
 };
 
 }  // namespace lbk

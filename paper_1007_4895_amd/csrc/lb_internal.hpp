@@ -118,6 +118,20 @@ struct BatchMulti {
     uint32_t seed;              // per-step seed of stochastic rounding (bf16 storage)
 };
 
+// A persistent launch of a batch: `nsteps` steps of every lattice, each
+// workgroup owning whole lattices (see k_batch_persistent).
+struct PersistArgs {
+    const StepArgs *desc;    // device: per lattice and side (low sides first), as for BatchMulti
+    const int32_t *wl_off;   // per workgroup: its first entry of wl (grid + 1 entries)
+    const int32_t *wl;       // lattice indices grouped by workgroup
+    const int32_t *lat;      // per lattice, 8 ints: item offset, items, projection offset, up, down, pair, 0, 0
+    const int32_t *items;    // update items (i0, j0, j1, descriptor index | set kind << 28)
+    const int32_t *proj;     // projection entries (i, j, lattice, 0): a lattice's up entries, then its down ones
+    int32_t nsteps;          // steps of this launch
+    int32_t cur;             // source copy of the first step
+    int64_t step0;           // step number of the first step (stochastic-rounding seeds)
+};
+
 // Arguments of the non-step kernels (one thread per node).
 struct NodeArgs {
     Geo g;

@@ -1414,6 +1414,85 @@ __global__ __launch_bounds__(128) void k_project_multi(const BatchMulti M) {
                                          (int64_t)(b - M.start[2]) * 128 + t);
 }
 
+// ---------------------------------------------------- persistent batch
+// One launch advances every lattice of a batch by P.nsteps steps.  Work-
+// group b owns the lattices P.wl[P.wl_off[b] .. P.wl_off[b + 1]) -- whole
+// lattices, assigned by the host largest-first by populations x nodes --
+// and loops over the steps with workgroup barriers only; no workgroup waits
+// on another.  Each update item runs on one wave holding all of its
+// populations (split over waves, an item would carry a barrier per row, and
+// waves could not take different items); the PERSIST_WAVES waves take a
+// lattice's items in turn, then, after a barrier, every thread takes the
+// lattice's projection entries in turn, and a barrier closes the step.  A
+// node's update and projection are the same arithmetic as in the other
+// launches, so the results are bit-identical to lb_step.
+constexpr int PERSIST_WAVES = 8;
+
+__device__ __forceinline__ uint32_t step_seed_dev(int64_t n) {
+    return uint32_t(uint64_t(n) * 0x9e3779b97f4a7c15ull >> 32);
+}
+
+// one update item of set SS on a single wave (i0 encodes the item shape as
+// for the batch update: wide, narrow lane groups, or wrapped 8-column groups)
+template <class ST, class SS>
+__device__ __forceinline__ void persist_item(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
+                                             const int j0, const int j1) {
+    if (i0 <= -NW_WRAP) update_item<ST, SS, SS, true, 1, true>(A, cur, seed, 0, j0, j1, -i0 - NW_WRAP);
+    else if (i0 < 0) update_item<ST, SS, SS, true, 1>(A, cur, seed, 0, j0, j1, -i0);
+    else update_item<ST, SS, SS, false, 1>(A, cur, seed, i0, j0, j1);
+}
+
+template <class ST, class S36, class S16>
+__global__ __launch_bounds__(64 * PERSIST_WAVES) __attribute__((amdgpu_waves_per_eu(2)))
+void k_batch_persistent(const PersistArgs P) {
+    using S9 = lbt::VSet<3, 2>;
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+    const int b = blockIdx.x;
+    const int l0 = P.wl_off[b], l1 = P.wl_off[b + 1];
+    for (int s = 0; s < P.nsteps; ++s) {
+        const int cur = P.cur ^ (s & 1);
+        const uint32_t seed = step_seed_dev(P.step0 + s);
+        for (int li = l0; li < l1; ++li) {
+            const int32_t *m = P.lat + 8 * P.wl[li];
+            const int ioff = __builtin_amdgcn_readfirstlane(m[0]), nit = __builtin_amdgcn_readfirstlane(m[1]);
+            for (int it = w; it < nit; it += PERSIST_WAVES) {
+                const int32_t *e = P.items + 4 * (ioff + it);
+                const int i0 = __builtin_amdgcn_readfirstlane(e[0]);
+                const int j0 = __builtin_amdgcn_readfirstlane(e[1]);
+                const int j1 = __builtin_amdgcn_readfirstlane(e[2]);
+                const int code = __builtin_amdgcn_readfirstlane(e[3]);
+                if (j0 >= j1) continue;
+                const StepArgs &A =
+                    *(const StepArgs *)((const __attribute__((address_space(4))) StepArgs *)P.desc + (code & 0x0fffffff));
+                const int kind = code >> 28;
+                if (kind == 0) persist_item<ST, S36>(A, cur, seed, i0, j0, j1);
+                else if (kind == 1) persist_item<ST, S16>(A, cur, seed, i0, j0, j1);
+                else persist_item<ST, S9>(A, cur, seed, i0, j0, j1);
+            }
+        }
+        __syncthreads();   // every update of this workgroup's lattices is written
+        for (int li = l0; li < l1; ++li) {
+            const int32_t *m = P.lat + 8 * P.wl[li];
+            const int32_t *pe = P.proj + 4 * m[2];
+            const int nup = m[3], ndown = m[4], pair = m[5];
+            if (pair == 0) {
+                const int64_t n = int64_t(nup) * S36::N + int64_t(ndown) * S9::N;
+                for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
+                    project_batch_entry<ST, S9, S36>(P.desc, pe, nup, ndown, cur, k);
+            } else if (pair == 1) {
+                const int64_t n = int64_t(nup) * S36::N + int64_t(ndown) * S16::N;
+                for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
+                    project_batch_entry<ST, S16, S36>(P.desc, pe, nup, ndown, cur, k);
+            } else if (pair == 2) {
+                const int64_t n = int64_t(nup) * S16::N + int64_t(ndown) * S9::N;
+                for (int64_t k = threadIdx.x; k < n; k += blockDim.x)
+                    project_batch_entry<ST, S9, S16>(P.desc, pe, nup, ndown, cur, k);
+            }
+        }
+        __syncthreads();   // the halos are written before the next step reads them
+    }
+}
+
 // ------------------------------------------------------- learned closure
 // Network 10 -> 64 -> 64 -> 8 (tanh, tanh, linear); parameter layout
 // W1[64][10], b1[64], W2[64][64], b2[64], W3[8][64], b3[8].

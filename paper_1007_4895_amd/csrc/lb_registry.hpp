@@ -47,10 +47,13 @@ struct KernelSet {
 // batch in one launch, for the sets D2Q36 of order eq6, D2Q16 of order eq4
 // and D2Q9 (order 2).
 using MultiFn = void (*)(const lbi::BatchMulti &, int grid, hipStream_t);
+using PersistFn = void (*)(const lbi::PersistArgs &, int grid, hipStream_t);
 struct MultiSet {
     int eq6, eq4;
     int waves;   // waves per block of the update (D2Q9 items per block)
     MultiFn update, project;
+    PersistFn persist;   // the persistent launch (k_batch_persistent)
+    int persist_waves;   // its waves per workgroup
 };
 
 struct Registry {

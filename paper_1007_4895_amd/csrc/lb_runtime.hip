@@ -1418,6 +1418,12 @@ struct lb_batch {
     hipGraphExec_t exec[2];
     hipEvent_t ev, t0, t1;
     int64_t nodes;
+    // persistent launches (lb_batch_set_persistent): per-workgroup lattice
+    // lists, per-lattice item and projection ranges
+    bool persistent = false;
+    const lbk::MultiSet *pms = nullptr;
+    int32_t *d_pwl_off = nullptr, *d_pwl = nullptr, *d_plat = nullptr, *d_pitems = nullptr, *d_pproj = nullptr;
+    int pgrid = 0;
 };
 
 namespace {
@@ -1440,6 +1446,89 @@ void batch_drop_graphs(lb_batch *B) {
         B->exec[p] = nullptr;
         B->graph[p] = nullptr;
     }
+}
+
+// Lists of the persistent launch: every lattice's update items (one wave
+// each, D2Q36 first) and projection entries, and the workgroups' lattices,
+// assigned largest-first (populations x nodes) to the least loaded of
+// min(lattices, CUs) workgroups.
+lb_status persist_build(lb_batch *B) {
+    const int nl = int(B->lat.size());
+    B->pms = nullptr;
+    for (int m = 0; m < B->reg.nmulti && !B->pms; ++m) {
+        const lbk::MultiSet &ms = B->reg.multi[m];
+        bool ok = ms.persist != nullptr;
+        for (lb_lattice *L : B->lat)
+            for (int s = 0; s < 2; ++s) {
+                const int n = L->n[s], e = L->eq[s];
+                ok = ok && ((n == 6 && e == ms.eq6) || (n == 4 && e == ms.eq4) || (n == 3 && e == 2));
+            }
+        if (ok) B->pms = &ms;
+    }
+    if (!B->pms) return fail(LB_EUNSUPPORTED, "no persistent batch kernel for these velocity sets and orders");
+    std::vector<int32_t> items, proj, lat(size_t(8) * nl, 0), f1, p1;
+    std::vector<std::pair<int, int>> runs;
+    std::vector<int> runcol;
+    std::vector<double> cost(nl, 0.0);
+    for (int l = 0; l < nl; ++l) {
+        lb_lattice *L = B->lat[l];
+        int np[2];
+        const int nfin = build_lists(L, f1, p1, np);
+        if (nfin) return fail(LB_EUNSUPPORTED, "lattice %d needs a finish pass (periodic rows or pressure columns): "
+                                               "not in persistent launches", l);
+        if (L->n[0] == L->n[1] && np[0] + np[1])
+            return fail(LB_EUNSUPPORTED, "lattice %d: equal sets with bands are not in persistent launches", l);
+        lat[8 * l] = int32_t(items.size() / 4);
+        const bool wrap = L->p.nx == 8 && L->p.xbc == LB_XBC_PERIODIC;
+        const int ng = wrap ? 8 : 64 / (L->p.nx + 4);
+        // the high (heavier) set's items first, so that waves start with them
+        for (int s : {1, 0}) {
+            const int kind = L->n[s] == 6 ? 0 : L->n[s] == 4 ? 1 : 2;
+            const int strip = B->strip[s] > 0 ? B->strip[s] : 4;
+            const int span = ng >= 2 ? ng * strip : strip;
+            set_runs(L, s, runs, runcol);
+            for (size_t r = 0; r < runs.size(); ++r)
+                for (int j = runs[r].first; j < runs[r].second; j += span) {
+                    items.insert(items.end(), {wrap ? -(strip + lbi::NW_WRAP) : ng >= 2 ? -strip : runcol[r], j,
+                                               std::min(j + span, runs[r].second), (s * nl + l) | (kind << 28)});
+                    cost[l] += double(L->Q[s]) * (std::min(j + span, runs[r].second) - j) *
+                               (ng >= 2 ? L->p.nx : 60);
+                }
+        }
+        lat[8 * l + 1] = int32_t(items.size() / 4) - lat[8 * l];
+        lat[8 * l + 2] = int32_t(proj.size() / 4);
+        for (int e = 0; e < np[0] + np[1]; ++e) proj.insert(proj.end(), {p1[2 * e], p1[2 * e + 1], l, 0});
+        lat[8 * l + 3] = np[0];
+        lat[8 * l + 4] = np[1];
+        const int nlo = L->n[0], nhi = L->n[1];
+        lat[8 * l + 5] = nhi == 6 ? (nlo == 3 ? 0 : 1) : 2;
+    }
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int nwg = std::max(1, std::min(nl, cus));
+    std::vector<int> order(nl);
+    for (int l = 0; l < nl; ++l) order[l] = l;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<double> load(nwg, 0.0);
+    std::vector<std::vector<int32_t>> own(nwg);
+    for (int l : order) {
+        const int g = int(std::min_element(load.begin(), load.end()) - load.begin());
+        load[g] += cost[l];
+        own[g].push_back(l);
+    }
+    std::vector<int32_t> off(1, 0), wl;
+    for (auto &o : own) {
+        wl.insert(wl.end(), o.begin(), o.end());
+        off.push_back(int32_t(wl.size()));
+    }
+    lb_status st = upload_list(off, B->d_pwl_off, B->stream);
+    if (st == LB_OK) st = upload_list(wl, B->d_pwl, B->stream);
+    if (st == LB_OK) st = upload_list(lat, B->d_plat, B->stream);
+    if (st == LB_OK) st = upload_list(items, B->d_pitems, B->stream);
+    if (st == LB_OK) st = upload_list(proj.empty() ? std::vector<int32_t>(4, 0) : proj, B->d_pproj, B->stream);
+    if (st != LB_OK) return st;
+    B->pgrid = nwg;
+    return LB_OK;
 }
 
 // merged work lists of every pair kind
@@ -1552,6 +1641,10 @@ lb_status batch_build(lb_batch *B) {
         if (!placed[g])
             return fail(LB_EUNSUPPORTED, "no batched update kernel for D2Q%d of order %d in this storage",
                         B->groups[g].n * B->groups[g].n, B->groups[g].eq);
+    if (B->persistent) {
+        lb_status st = persist_build(B);
+        if (st != LB_OK) return st;
+    }
     HIPCHK(hipStreamSynchronize(B->stream));
     for (size_t l = 0; l < B->lat.size(); ++l) B->gen[l] = B->lat[l]->gen;
     return LB_OK;
@@ -1616,6 +1709,35 @@ lb_status batch_launch(lb_batch *B, int cur, uint32_t seed) {
     return LB_OK;
 }
 
+// n steps of every lattice from copy B->cur, step numbers from step0: one
+// set of launches per step, or persistent launches of up to 4096 steps
+lb_status batch_steps(lb_batch *B, int64_t n, int64_t step0) {
+    int64_t k = 0;
+    while (k < n) {
+        if (B->persistent) {
+            PersistArgs a{};
+            a.desc = B->d_desc[0];
+            a.wl_off = B->d_pwl_off;
+            a.wl = B->d_pwl;
+            a.lat = B->d_plat;
+            a.items = B->d_pitems;
+            a.proj = B->d_pproj;
+            a.nsteps = int32_t(std::min<int64_t>(4096, n - k));
+            a.cur = B->cur;
+            a.step0 = step0 + k;
+            B->pms->persist(a, B->pgrid, B->stream);
+            B->cur ^= a.nsteps & 1;
+            k += a.nsteps;
+        } else {
+            lb_status st = batch_launch(B, B->cur, step_seed(step0 + k));
+            if (st != LB_OK) return st;
+            B->cur ^= 1;
+            ++k;
+        }
+    }
+    return LB_OK;
+}
+
 lb_status batch_check(lb_batch *B) {
     bool stale = false;
     for (size_t l = 0; l < B->lat.size(); ++l) {
@@ -1651,10 +1773,9 @@ lb_status batch_run(lb_batch *B, int64_t steps) {
             const int par = B->cur;
             if (!B->exec[par]) {
                 HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-                lb_status st = LB_OK;
                 // (a replayed graph repeats its segment's seeds)
-                for (int q = 0; q < B->seg && st == LB_OK; ++q)
-                    st = batch_launch(B, par ^ (q & 1), step_seed(B->lat[0]->step + k + q));
+                lb_status st = batch_steps(B, B->seg, B->lat[0]->step + k);
+                B->cur = par;
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(B->stream, &g);
                 if (st != LB_OK) {
@@ -1670,10 +1791,9 @@ lb_status batch_run(lb_batch *B, int64_t steps) {
             k += B->seg;
         }
     }
-    for (; k < steps; ++k) {
-        lb_status st = batch_launch(B, B->cur, step_seed(B->lat[0]->step + k));
+    if (k < steps) {
+        lb_status st = batch_steps(B, steps - k, B->lat[0]->step + k);
         if (st != LB_OK) return st;
-        B->cur ^= 1;
     }
     HIPCHK(hipGetLastError());
     for (lb_lattice *L : B->lat) {
@@ -1782,11 +1902,27 @@ void lb_batch_destroy(lb_batch *B) {
     }
     for (auto &G : B->groups)
         if (G.d_items) (void)hipFree(G.d_items);
+    for (int32_t *p : {B->d_pwl_off, B->d_pwl, B->d_plat, B->d_pitems, B->d_pproj})
+        if (p) (void)hipFree(p);
     if (B->d_desc[0]) (void)hipFree(B->d_desc[0]);
     if (B->ev) (void)hipEventDestroy(B->ev);
     if (B->t0) (void)hipEventDestroy(B->t0);
     if (B->t1) (void)hipEventDestroy(B->t1);
     delete B;
+}
+
+lb_status lb_batch_set_persistent(lb_batch *B, int32_t enable) {
+    if (!B) return fail(LB_EINVAL, "null batch");
+    const bool on = enable != 0;
+    if (on == B->persistent) return LB_OK;
+    B->persistent = on;
+    lb_status st = batch_build(B);
+    if (st != LB_OK) {
+        B->persistent = false;
+        lb_status st2 = batch_build(B);
+        return st2 != LB_OK ? st2 : st;
+    }
+    return LB_OK;
 }
 
 lb_status lb_batch_set_graph(lb_batch *B, int32_t segment_steps) {
@@ -1836,10 +1972,7 @@ lb_status lb_batch_autotune(lb_batch *B, int32_t steps, int32_t rows_out[2]) {
             // timed twice, the faster pass counting
             for (int rep = 0; rep < 2; ++rep) {
                 HIPCHK(hipEventRecord(B->t0, B->stream));
-                for (int k = 0; k < steps; ++k) {
-                    if ((st = batch_launch(B, B->cur, step_seed(k))) != LB_OK) return st;
-                    B->cur ^= 1;
-                }
+                if ((st = batch_steps(B, steps, 0)) != LB_OK) return st;
                 HIPCHK(hipEventRecord(B->t1, B->stream));
                 HIPCHK(hipEventSynchronize(B->t1));
                 float ms = 0;
@@ -1880,7 +2013,7 @@ lb_status lb_batch_info(const lb_batch *B, int64_t *nodes, int32_t *launches_per
     }
     for (auto &K : B->kinds) nl += (!K.merged && K.nup + K.ndown > 0) + (K.nfin > 0);
     if (nodes) *nodes = B->nodes;
-    if (launches_per_step) *launches_per_step = nl;
+    if (launches_per_step) *launches_per_step = B->persistent ? 0 : nl;
     if (kinds) *kinds = int32_t(B->kinds.size());
     return LB_OK;
 }

@@ -106,6 +106,7 @@ def lib():
             "lb_batch_create": (C.c_int, [C.POINTER(_vp), C.c_int32, _vp, C.POINTER(_vp)]),
             "lb_batch_destroy": (None, [_vp]),
             "lb_batch_set_graph": (C.c_int, [_vp, C.c_int32]),
+            "lb_batch_set_persistent": (C.c_int, [_vp, C.c_int32]),
             "lb_batch_step": (C.c_int, [_vp, C.c_int64]),
             "lb_batch_set_strip_rows": (C.c_int, [_vp, C.c_int32, C.c_int32]),
             "lb_batch_autotune": (C.c_int, [_vp, C.c_int32, _ip]),
@@ -377,6 +378,11 @@ class Batch:
 
     def set_graph(self, segment_steps):
         _check(lib().lb_batch_set_graph(self._h, int(segment_steps)))
+
+    def set_persistent(self, on=True):
+        """One persistent launch per run of steps (workgroups own whole
+        lattices and loop over the steps)."""
+        _check(lib().lb_batch_set_persistent(self._h, 1 if on else 0))
 
     def step(self, n=1):
         _check(lib().lb_batch_step(self._h, int(n)))

@@ -221,3 +221,80 @@ def test_c5_channel_vs_oracle(oracle, lb):
     print(f"channel {k} (ny={c['ny']}, Kn={c['kn']:.3g}): relative velocity error {err:.2e}")
     assert err < 1e-5
     B.close()
+
+
+# persistent launches take lattices without a finish pass
+PERSIST = [c for c in MIXED if not (c[4].get("ybc") or c[4].get("xbc"))]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_persistent_batch_bit_identical_to_single(lb, storage):
+    # one launch per run of steps, workgroups owning whole lattices: the same
+    # bits as stepping every lattice on its own (stochastic-rounding seeds
+    # included for bf16, whose kernels are built for D2Q9 and D2Q36 only)
+    cases = PERSIST if storage != "bf16" else [c for c in PERSIST if set(c[2][::2]) <= {3, 6}]
+    A = [_make(lb, c, storage, 400 + k) for k, c in enumerate(cases)]
+    S = [_make(lb, c, storage, 400 + k) for k, c in enumerate(cases)]
+    B = lb.Batch(A)
+    B.set_persistent(True)
+    _, launches, _ = B.info()
+    assert launches == 0
+    print(f"persistent batch {storage}: direct", flush=True)
+    B.step(7)
+    for L in S:
+        L.step(7)
+    assert all(_same(a, s) for a, s in zip(A, S))
+    # graph segments of 4 steps (one captured launch each) and a tail; a
+    # replayed segment repeats its stochastic-rounding seeds, so bf16 stays
+    # on direct launches here
+    if storage != "bf16":
+        B.set_graph(4)
+    B.step(11)
+    for L in S:
+        L.step(11)
+    assert all(_same(a, s) for a, s in zip(A, S))
+    # strips from the autotuner in this mode (states are restored)
+    B.autotune(3)
+    assert all(_same(a, s) for a, s in zip(A, S))
+    B.step(6)
+    for L in S:
+        L.step(6)
+    assert all(_same(a, s) for a, s in zip(A, S))
+    # back to the per-step launches
+    B.set_persistent(False)
+    B.step(3)
+    for L in S:
+        L.step(3)
+    assert all(_same(a, s) for a, s in zip(A, S))
+    B.close()
+
+
+def test_persistent_batch_refuses_finish_passes(lb):
+    A = [_make(lb, c, "f64", 500 + k) for k, c in enumerate(MIXED)]
+    B = lb.Batch(A)
+    with pytest.raises(lb.LBError):
+        B.set_persistent(True)
+    # the batch keeps its per-step launches
+    S = [_make(lb, c, "f64", 500 + k) for k, c in enumerate(MIXED)]
+    B.step(3)
+    for L in S:
+        L.step(3)
+    assert all(_same(a, s) for a, s in zip(A, S))
+    B.close()
+
+
+def test_c5_persistent_bit_identical(lb):
+    # the 128-channel workload in persistent launches (graph segments, as the
+    # benchmark runs it) against per-channel stepping
+    cases, A = _c5(lb)
+    _, S = _c5(lb)
+    B = lb.Batch(A)
+    B.set_persistent(True)
+    B.autotune(5)
+    B.set_graph(20)
+    B.step(60)
+    for L in S:
+        L.step(60)
+    bad = [k for k, (a, s) in enumerate(zip(A, S)) if not _same(a, s)]
+    assert not bad, bad
+    B.close()
