@@ -10,10 +10,29 @@ namespace lbk {
 template <class ST, class S, class O>
 struct Inst {
     static int nodes_grid(const NodeArgs &a) { return (a.g.nrow * a.g.nx + 255) / 256; }
+    // FP32 / BF16 lattices whose storage reference varies by column group
+    // take the kernels' XS variant
+    static bool xs(const StepArgs &a) {
+        if constexpr (sizeof(typename ST::M) == 4) return a.dshift != 0.0;
+        else return false;
+    }
     static void update(const StepArgs &a, int grid, hipStream_t s) {
+        if constexpr (sizeof(typename ST::M) == 4) {
+            if (xs(a)) {
+                hipLaunchKernelGGL((k_update<ST, S, O, true>), dim3(grid), dim3(64 * update_split<S>()), 0, s, a);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_update<ST, S, O>), dim3(grid), dim3(64 * update_split<S>()), 0, s, a);
     }
     static void update_timed(const StepArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+        if constexpr (sizeof(typename ST::M) == 4) {
+            if (xs(a)) {
+                hipExtLaunchKernelGGL((k_update<ST, S, O, true>), dim3(grid), dim3(64 * update_split<S>()), 0, s, e0,
+                                      e1, 0, a);
+                return;
+            }
+        }
         hipExtLaunchKernelGGL((k_update<ST, S, O>), dim3(grid), dim3(64 * update_split<S>()), 0, s, e0, e1, 0, a);
     }
     static void finish(const StepArgs &a, int grid, hipStream_t s) {
@@ -36,6 +55,17 @@ struct Inst {
     }
     static void update_pair(const StepArgs &l, const StepArgs &h, int nb_h, int nb_l, hipStream_t s, hipEvent_t e0,
                             hipEvent_t e1) {
+        if constexpr (sizeof(typename ST::M) == 4) {
+            if (xs(l)) {
+                if (e0)
+                    hipExtLaunchKernelGGL((k_update_pair<ST, S, O, true>), dim3(nb_h + nb_l), dim3(64 * pair_split<O>()),
+                                          0, s, e0, e1, 0, l, h, nb_h);
+                else
+                    hipLaunchKernelGGL((k_update_pair<ST, S, O, true>), dim3(nb_h + nb_l), dim3(64 * pair_split<O>()),
+                                       0, s, l, h, nb_h);
+                return;
+            }
+        }
         if (e0)
             hipExtLaunchKernelGGL((k_update_pair<ST, S, O>), dim3(nb_h + nb_l), dim3(64 * pair_split<O>()), 0, s, e0,
                                   e1, 0, l, h, nb_h);

@@ -48,6 +48,20 @@ struct Phys {
     double shear;      // YBC_SHEAR: velocity gradient du/dy imposed above the top row
 };
 
+// Storage shift: populations are stored as f - w_alpha s(i), with the
+// reference density s(i) = s0 + ds * g(i) constant over each group
+// g(i) = floor(i / SHIFT_GROUP) of SHIFT_GROUP columns -- the columns one
+// work item of the update kernel owns, so that every node an item writes
+// shares its shift.  ds = 0 except for pressure-driven lattices stored in
+// FP32 / BF16, whose reference follows the imposed density ramp (the
+// stored deviations then carry no density ramp); FP64 stores f (s = 0).
+constexpr int SHIFT_GROUP = 60;
+struct Shift {
+    double s0, ds;
+};
+__host__ __device__ inline int shift_group(int i) { return i >= 0 ? i / SHIFT_GROUP : (i - (SHIFT_GROUP - 1)) / SHIFT_GROUP; }
+__host__ __device__ inline double shift_at(const Shift &s, int i) { return s.s0 + s.ds * double(shift_group(i)); }
+
 // Per-set kernel constants, in double and float: nu_p = x_p dt and
 // k_p = |nu_p| (1 - |nu_p|) / 2 for the p-th 1D abscissa.
 struct SetK {
@@ -75,7 +89,8 @@ struct StepArgs {
     Phys ph;
     Buf self, other;     // the set this kernel evolves, and its partner
     SetK ks;             // constants of `self`
-    double rho_shift;    // storage shift (rho_ref for F32/BF16, 0 for F64)
+    double rho_shift;    // storage shift s0 (Shift; rho_ref for F32/BF16, 0 for F64)
+    double dshift;       // storage shift step per column group (Shift::ds)
     int32_t cur;         // source copy; the kernel writes copy cur ^ 1
     int32_t self_high;   // 1 if `self` is the high set
     int32_t nitems;      // work items (64 columns x a strip of rows)
@@ -138,6 +153,7 @@ struct NodeArgs {
     Phys ph;
     Buf self, other;
     double rho_shift;
+    double dshift;
     int32_t cur;
     int32_t self_high;
     int32_t which;       // set index of `self` in the caller's numbering

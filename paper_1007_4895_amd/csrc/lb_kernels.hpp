@@ -422,16 +422,23 @@ __device__ __forceinline__ typename ST::S *plane0(const Buf &b, int copy) {
     return reinterpret_cast<typename ST::S *>(b.base[copy]) + b.rowbase;
 }
 
+template <class A>
+__device__ __forceinline__ Shift sh_of(const A &a) { return Shift{a.rho_shift, a.dshift}; }
+
 template <class ST, class SS>
-__device__ void load_node_d(const Buf &b, int copy, int i, int j, double shift, double *f) {
+__device__ void load_node_d(const Buf &b, int copy, int i, int j, const Shift &sh, double *f) {
     const typename ST::S *p = plane0<ST, SS>(b, copy) + (int64_t)(j + 2) * b.pitch + i;
+    const double shift = shift_at(sh, i);
 #pragma unroll
     for (int a = 0; a < SS::Q; ++a) f[a] = ST::ldd(p + a * b.plane) + w_of<SS>(a) * shift;
 }
 
+// absolute populations f to node / ghost entry (i, j), shifted by the
+// reference of column i
 template <class ST, class SS>
-__device__ void store_node_d(const Buf &b, int copy, int i, int j, double shift, const double *f) {
+__device__ void store_node_d(const Buf &b, int copy, int i, int j, const Shift &sh, const double *f) {
     typename ST::S *p = plane0<ST, SS>(b, copy) + (int64_t)(j + 2) * b.pitch + i;
+    const double shift = shift_at(sh, i);
 #pragma unroll
     for (int a = 0; a < SS::Q; ++a) ST::std_(p + a * b.plane, f[a] - w_of<SS>(a) * shift);
 }
@@ -442,7 +449,7 @@ __device__ void store_node_d(const Buf &b, int copy, int i, int j, double shift,
 // boundary columns (equilibrium at the prescribed density with the edge
 // node's velocity plus the edge node's non-equilibrium part).
 template <class ST, class SS>
-__device__ void emit_node(const Buf &b, int copy, int i, int j, double shift, const double *f, bool own,
+__device__ void emit_node(const Buf &b, int copy, int i, int j, const Shift &shift, const double *f, bool own,
                           const Geo &g, const Phys &ph) {
     if (own) store_node_d<ST, SS>(b, copy, i, j, shift, f);
     if (g.ybc == YBC_WALLS) {
@@ -501,7 +508,7 @@ __device__ void emit_node(const Buf &b, int copy, int i, int j, double shift, co
 // images, and (Hermite interface) its projection into the partner set OO
 // wherever a stencil of OO reads it.
 template <class ST, class SS, class OO>
-__device__ void finish_node(const Buf &self, const Buf &other, int copy, int i, int j, double shift,
+__device__ void finish_node(const Buf &self, const Buf &other, int copy, int i, int j, const Shift &shift,
                             const double *f, bool own, bool proj, const Geo &g, const Phys &ph) {
     emit_node<ST, SS>(self, copy, i, j, shift, f, own, g, ph);
     if constexpr (OO::Q > 0) {
@@ -570,7 +577,19 @@ constexpr int update_waves() { return SS::Q == 36 ? LB_WAVES36 : SS::Q == 16 ? 4
 template <class SS>
 constexpr int pair_waves() { return SS::Q == 36 ? LB_WAVES36_PAIR : update_waves<SS>(); }
 
-template <class ST, class SS, class OO, int WV, bool NW = false, int SPL = update_split<SS>(), bool WR = false>
+// load of a stored population, moved by w * dl to another storage
+// reference when XS (FP32 arithmetic, fused within the expression)
+template <class ST, bool XS>
+__device__ __forceinline__ typename ST::M ld_x(__amdgpu_buffer_rsrc_t r, unsigned vo, unsigned so,
+                                               typename ST::M w, typename ST::M dl) {
+#pragma clang fp contract(on)
+    typename ST::M v = ST::bld(r, vo, so);
+    if constexpr (XS) v = v + w * dl;
+    return v;
+}
+
+template <class ST, class SS, class OO, int WV, bool NW = false, int SPL = update_split<SS>(), bool WR = false,
+          bool XS = false>
 __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
                                             const int j0, const int j1, const int lane, const int S = 0);
 
@@ -578,7 +597,8 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 // narrow lattice) 64 / (nx + 4) lane groups of nx + 4 columns each, group
 // g marching rows j0 + g S .. j0 + (g + 1) S (clipped to j1); SPL waves
 // share the populations (the result does not depend on SPL)
-template <class ST, class SS, class OO, bool NW = false, int SPL = update_split<SS>(), bool WR = false>
+template <class ST, class SS, class OO, bool NW = false, int SPL = update_split<SS>(), bool WR = false,
+          bool XS = false>
 __device__ __forceinline__ void update_item(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
                                             const int j0, const int j1, const int S = 0) {
     constexpr int SPLIT = SPL;
@@ -587,21 +607,24 @@ __device__ __forceinline__ void update_item(const StepArgs &A, const int cur, co
     // for its own abscissae, so every population's upwind direction and
     // constants are known at compile time
     const int wv = SPLIT > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6) : 0;
-    if (wv == 0) update_rows<ST, SS, OO, 0, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
+    if (wv == 0) update_rows<ST, SS, OO, 0, NW, SPL, WR, XS>(A, cur, seed, i0, j0, j1, lane, S);
     if constexpr (SPLIT > 1) {
-        if (wv == 1) update_rows<ST, SS, OO, 1, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 1) update_rows<ST, SS, OO, 1, NW, SPL, WR, XS>(A, cur, seed, i0, j0, j1, lane, S);
     }
     if constexpr (SPLIT > 2) {
-        if (wv == 2) update_rows<ST, SS, OO, 2, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 2) update_rows<ST, SS, OO, 2, NW, SPL, WR, XS>(A, cur, seed, i0, j0, j1, lane, S);
     }
     if constexpr (SPLIT > 3) {
-        if (wv == 3) update_rows<ST, SS, OO, 3, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
-        if (wv == 4) update_rows<ST, SS, OO, 4, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
-        if (wv == 5) update_rows<ST, SS, OO, 5, NW, SPL, WR>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 3) update_rows<ST, SS, OO, 3, NW, SPL, WR, XS>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 4) update_rows<ST, SS, OO, 4, NW, SPL, WR, XS>(A, cur, seed, i0, j0, j1, lane, S);
+        if (wv == 5) update_rows<ST, SS, OO, 5, NW, SPL, WR, XS>(A, cur, seed, i0, j0, j1, lane, S);
     }
 }
 
-template <class ST, class SS, class OO>
+// XS: the storage reference varies by column group (FP32 / BF16 pressure
+// lattices): the variant that moves other groups' loaded values to the
+// item's reference (a kernel of its own, so the common one is unchanged)
+template <class ST, class SS, class OO, bool XS = false>
 __global__ __launch_bounds__(64 * update_split<SS>())
 __attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : update_waves<SS>())))
 void k_update(const StepArgs A) {
@@ -612,7 +635,7 @@ void k_update(const StepArgs A) {
     if (it >= A.nitems) return;
     const int i0 = A.items[4 * it], j0 = A.items[4 * it + 1], j1 = A.items[4 * it + 2];
     if (j0 >= j1) return;   // padding item
-    update_item<ST, SS, OO>(A, A.cur, A.seed, i0, j0, j1);
+    update_item<ST, SS, OO, false, update_split<SS>(), false, XS>(A, A.cur, A.seed, i0, j0, j1);
 }
 
 // Both sets of a lattice in one launch, for a D2Q9 low set (one wave per
@@ -621,7 +644,7 @@ void k_update(const StepArgs A) {
 // D2Q9 item.  The two sets touch disjoint buffers, and one launch lets
 // their waves share the machine instead of running back to back.
 
-template <class ST, class LS, class HS>
+template <class ST, class LS, class HS, bool XS = false>
 __global__ __launch_bounds__(64 * pair_split<HS>())
 __attribute__((amdgpu_waves_per_eu(sizeof(typename ST::M) == 8 ? 2 : pair_waves<HS>())))
 void k_update_pair(const StepArgs L, const StepArgs H, const int nb_h) {
@@ -633,7 +656,7 @@ void k_update_pair(const StepArgs L, const StepArgs H, const int nb_h) {
             if (it >= H.nitems) return;
             const int i0 = H.items[4 * it], j0 = H.items[4 * it + 1], j1 = H.items[4 * it + 2];
             if (j0 >= j1) return;
-            update_item<ST, HS, LS, false, SPLIT>(H, H.cur, H.seed, i0, j0, j1);
+            update_item<ST, HS, LS, false, SPLIT, false, XS>(H, H.cur, H.seed, i0, j0, j1);
         } else {
             // low items: XCD slab (b' mod 8) of L.chunk items, SPLIT per block
             const int bl = b - nb_h;
@@ -644,7 +667,8 @@ void k_update_pair(const StepArgs L, const StepArgs H, const int nb_h) {
             if (it >= L.nitems) return;
             const int i0 = L.items[4 * it], j0 = L.items[4 * it + 1], j1 = L.items[4 * it + 2];
             if (j0 >= j1) return;
-            update_rows<ST, LS, HS, 0>(L, L.cur, L.seed, i0, j0, j1, threadIdx.x & 63);
+            update_rows<ST, LS, HS, 0, false, update_split<LS>(), false, XS>(L, L.cur, L.seed, i0, j0, j1,
+                                                                          threadIdx.x & 63);
         }
     }
 }
@@ -676,8 +700,18 @@ __device__ __forceinline__ void batch_item(const BatchMulti &M, const int slot, 
     // a negative first column marks a narrow lattice's item: -i0 rows per
     // lane group, or -i0 - NW_WRAP for an 8-column periodic lattice whose
     // x neighbours wrap inside 8-lane groups
-    if (i0 <= -NW_WRAP) update_item<ST, SS, SS, true, multi_split<SS>(), true>(A, M.cur, M.seed, 0, j0, j1, -i0 - NW_WRAP);
-    else if (i0 < 0) update_item<ST, SS, SS, true, multi_split<SS>()>(A, M.cur, M.seed, 0, j0, j1, -i0);
+    if (i0 <= -NW_WRAP) {
+        update_item<ST, SS, SS, true, multi_split<SS>(), true>(A, M.cur, M.seed, 0, j0, j1, -i0 - NW_WRAP);
+        return;
+    }
+    if constexpr (sizeof(typename ST::M) == 4) {
+        if (A.dshift != 0.0) {
+            if (i0 < 0) update_item<ST, SS, SS, true, multi_split<SS>(), false, true>(A, M.cur, M.seed, 0, j0, j1, -i0);
+            else update_item<ST, SS, SS, false, multi_split<SS>(), false, true>(A, M.cur, M.seed, i0, j0, j1);
+            return;
+        }
+    }
+    if (i0 < 0) update_item<ST, SS, SS, true, multi_split<SS>()>(A, M.cur, M.seed, 0, j0, j1, -i0);
     else update_item<ST, SS, SS, false, multi_split<SS>()>(A, M.cur, M.seed, i0, j0, j1);
 }
 
@@ -721,7 +755,7 @@ void k_update_multi(const BatchMulti M) {
         }                                                                                \
     }
 
-template <class ST, class SS, class OO, int WV, bool NW, int SPL, bool WR>
+template <class ST, class SS, class OO, int WV, bool NW, int SPL, bool WR, bool XS>
 __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, const uint32_t seed, const int i0,
                                             const int j0, const int j1, const int lane, const int S) {
     // multiply-adds are fused within an expression only (not across
@@ -799,6 +833,17 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
         __builtin_amdgcn_make_buffer_rsrc(uniform(A.self.base[cur ^ 1]), 0, int(nbytes), 0x00020000);
     const unsigned OOB = nbytes;
     const unsigned vl = unsigned(min(max(col, -2), nx + 1) + 2) * EB;
+    // storage reference of this item: every node it owns lies in one column
+    // group (a wide item's 60 columns start at a multiple of 60, a narrow
+    // lattice has fewer than 60 columns).  XS: values of lanes in another
+    // group (halo lanes, ghost columns) are moved to this item's reference
+    // as they are loaded, + w_alpha (s(column) - s(item))
+    const Shift shv = sh_of(A);
+    const double s_item = XS ? shift_at(shv, NW ? 0 : i0) : A.rho_shift;
+    T dl = T(0);
+    if constexpr (XS) dl = T(shift_at(shv, min(max(col, -2), nx + 1)) - s_item);
+#define LB_LD(a, vo, so) \
+    ld_x<ST, XS>(rs, vo, so, T(TB::rule.w[(a) % N] * TB::rule.w[(a) / N]), dl)
 #define LB_SOFF(a, j) unsigned(((int64_t)(a) * P + rb + (int64_t)((j) + 2) * pitch) * EB)
     // narrow lattices: the row is per lane, so it moves into the vector
     // offset and the scalar offset keeps the population only
@@ -830,7 +875,8 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 #pragma unroll
     for (int k = 0; k < QW; ++k) {
         const double xq = TB::rule.x[q0 + k / N];
-        nw[k] = ST::bld(rs, LB_VO(vl, xq < 0.0 ? jl0 + 2 : jl0 + 1), LB_SO(LB_POP(k), xq < 0.0 ? jl0 + 2 : jl0 + 1));
+        nw[k] = LB_LD(LB_POP(k), LB_VO(vl, xq < 0.0 ? jl0 + 2 : jl0 + 1),
+                      LB_SO(LB_POP(k), xq < 0.0 ? jl0 + 2 : jl0 + 1));
     }
     // y window per population: c = f_j; for xi_y > 0: s1 = f_j - f_{j-1},
     // s2 = minmod(f_{j-1} - f_{j-2}, f_j - f_{j-1}); for xi_y < 0:
@@ -841,21 +887,21 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
         const int a = LB_POP(k);
         const double xq = TB::rule.x[q0 + k / N];
         if (xq > 0.0) {
-            T fm2 = ST::bld(rs, LB_VO(vl, jl0 - 2), LB_SO(a, jl0 - 2));
-            T fm1 = ST::bld(rs, LB_VO(vl, jl0 - 1), LB_SO(a, jl0 - 1));
-            T f0 = ST::bld(rs, LB_VO(vl, jl0), LB_SO(a, jl0));
+            T fm2 = LB_LD(a, LB_VO(vl, jl0 - 2), LB_SO(a, jl0 - 2));
+            T fm1 = LB_LD(a, LB_VO(vl, jl0 - 1), LB_SO(a, jl0 - 1));
+            T f0 = LB_LD(a, LB_VO(vl, jl0), LB_SO(a, jl0));
             c[k] = f0;
             s1[k] = f0 - fm1;
             s2[k] = minmod(fm1 - fm2, f0 - fm1);
         } else if (xq < 0.0) {
-            T fm1 = ST::bld(rs, LB_VO(vl, jl0 - 1), LB_SO(a, jl0 - 1));
-            T f0 = ST::bld(rs, LB_VO(vl, jl0), LB_SO(a, jl0));
-            T fp1 = ST::bld(rs, LB_VO(vl, jl0 + 1), LB_SO(a, jl0 + 1));
+            T fm1 = LB_LD(a, LB_VO(vl, jl0 - 1), LB_SO(a, jl0 - 1));
+            T f0 = LB_LD(a, LB_VO(vl, jl0), LB_SO(a, jl0));
+            T fp1 = LB_LD(a, LB_VO(vl, jl0 + 1), LB_SO(a, jl0 + 1));
             c[k] = f0;
             s1[k] = fp1;
             s2[k] = minmod(fp1 - f0, f0 - fm1);
         } else {
-            c[k] = ST::bld(rs, LB_VO(vl, jl0), LB_SO(a, jl0));
+            c[k] = LB_LD(a, LB_VO(vl, jl0), LB_SO(a, jl0));
             s1[k] = T(0);
             s2[k] = T(0);
         }
@@ -867,7 +913,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
     const bool per_x = g.xbc == XBC_PERIODIC;
     const bool wave_img = per_x && (NW || i0 < 2 || i0 + 60 > nx - 2);   // uniform
 
-    const T rho_shift = T(A.rho_shift);
+    const T rho_shift = T(s_item);
     const T om0 = T(A.ph.omega0);
     const T om_rho = T(A.ph.omega0 / A.ph.rho_ref);
     const T dtT = T(A.ph.dt), gxT = T(A.ph.gx), gyT = T(A.ph.gy);
@@ -1033,7 +1079,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                     c[k] = nw[k];
                 }
                 // next row of this population (zero-cost past the strip end)
-                nw[k] = ST::bld(rs, LB_VO(vln, xq < 0.0 ? j + 3 : j + 2), LB_SO(a, xq < 0.0 ? j + 3 : j + 2));
+                nw[k] = LB_LD(a, LB_VO(vln, xq < 0.0 ? j + 3 : j + 2), LB_SO(a, xq < 0.0 ? j + 3 : j + 2));
 
                 LB_ST(LB_VO(vs, j), LB_SO(a, j), acc)
                 accq[p] = acc;
@@ -1112,6 +1158,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 #undef LB_VO
 #undef LB_SO
 #undef LB_POP
+#undef LB_LD
 }
 #undef LB_ST
 
@@ -1223,32 +1270,33 @@ __device__ double feq_one(double rho, double ux, double uy, int t) {
 // store one population t of set SS at node (i, j) and at every ghost entry
 // standing for it (the per-population form of emit_node)
 template <class ST, class SS>
-__device__ void emit_pop(const Buf &b, int copy, int i, int j, double shift, int t, double v, double rho,
+__device__ void emit_pop(const Buf &b, int copy, int i, int j, const Shift &sh, int t, double v, double rho,
                          double ux, double uy, const Geo &g, const Phys &ph) {
     typename ST::S *p0 = plane0<ST, SS>(b, copy) + (int64_t)t * b.plane;
-    const double sv = v - w_of<SS>(t) * shift;
-    auto put = [&](int ii, int jj, double x) { ST::std_(p0 + (int64_t)(jj + 2) * b.pitch + ii, x); };
-    put(i, j, sv);
+    // absolute value x to entry (ii, jj), shifted by the reference of column ii
+    auto put = [&](int ii, int jj, double x) {
+        ST::std_(p0 + (int64_t)(jj + 2) * b.pitch + ii, x - w_of<SS>(t) * shift_at(sh, ii));
+    };
+    put(i, j, v);
     if (g.ybc == YBC_WALLS) {
-        if (j == 0) { put(i, -1, sv); put(i, -2, sv); }
-        if (j == g.ny) { put(i, g.ny + 1, sv); put(i, g.ny + 2, sv); }
+        if (j == 0) { put(i, -1, v); put(i, -2, v); }
+        if (j == g.ny) { put(i, g.ny + 1, v); put(i, g.ny + 2, v); }
     } else if (g.ybc == YBC_SHEAR) {
-        if (j == 0) { put(i, -1, sv); put(i, -2, sv); }
+        if (j == 0) { put(i, -1, v); put(i, -2, v); }
         if (j == g.ny) {
             const double neq = v - feq_one<SS>(rho, ux, uy, t);
-            put(i, g.ny + 1, feq_one<SS>(rho, ux + ph.shear, uy, t) + neq - w_of<SS>(t) * shift);
-            put(i, g.ny + 2, feq_one<SS>(rho, ux + 2.0 * ph.shear, uy, t) + neq - w_of<SS>(t) * shift);
+            put(i, g.ny + 1, feq_one<SS>(rho, ux + ph.shear, uy, t) + neq);
+            put(i, g.ny + 2, feq_one<SS>(rho, ux + 2.0 * ph.shear, uy, t) + neq);
         }
     } else {
-        if (j < 2) put(i, j + g.nrow, sv);
-        if (j >= g.nrow - 2) put(i, j - g.nrow, sv);
+        if (j < 2) put(i, j + g.nrow, v);
+        if (j >= g.nrow - 2) put(i, j - g.nrow, v);
     }
     if (g.xbc == XBC_PERIODIC) {
-        if (i < 2) put(i + g.nx, j, sv);
-        if (i >= g.nx - 2) put(i - g.nx, j, sv);
+        if (i < 2) put(i + g.nx, j, v);
+        if (i >= g.nx - 2) put(i - g.nx, j, v);
     } else if (i == 0 || i == g.nx - 1) {
-        const double gv = feq_one<SS>(i == 0 ? ph.rho_in : ph.rho_out, ux, uy, t) + (v - feq_one<SS>(rho, ux, uy, t)) -
-                          w_of<SS>(t) * shift;
+        const double gv = feq_one<SS>(i == 0 ? ph.rho_in : ph.rho_out, ux, uy, t) + (v - feq_one<SS>(rho, ux, uy, t));
         if (i == 0) { put(-1, j, gv); put(-2, j, gv); }
         else { put(g.nx, j, gv); put(g.nx + 1, j, gv); }
     }
@@ -1265,15 +1313,15 @@ __device__ __forceinline__ void finish_pop(const StepArgs &A, const int cur, con
     if (set == 0) {
         if (t >= LS::Q) return;
         double f[LS::Q];
-        load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, f);
+        load_node_d<ST, LS>(A.self, copy, i, j, sh_of(A), f);
         moments_d<LS>(f, rho, ux, uy);
-        emit_pop<ST, LS>(A.self, copy, i, j, A.rho_shift, t, f[t], rho, ux, uy, A.g, A.ph);
+        emit_pop<ST, LS>(A.self, copy, i, j, sh_of(A), t, f[t], rho, ux, uy, A.g, A.ph);
     } else {
         if (t >= HS::Q) return;
         double f[HS::Q];
-        load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, f);
+        load_node_d<ST, HS>(A.other, copy, i, j, sh_of(A), f);
         moments_d<HS>(f, rho, ux, uy);
-        emit_pop<ST, HS>(A.other, copy, i, j, A.rho_shift, t, f[t], rho, ux, uy, A.g, A.ph);
+        emit_pop<ST, HS>(A.other, copy, i, j, sh_of(A), t, f[t], rho, ux, uy, A.g, A.ph);
     }
 }
 
@@ -1313,18 +1361,18 @@ __device__ __forceinline__ void project_entry(const StepArgs &A, const int cur, 
     double rho, ux, uy;
     if (up) {
         double fs[LS::Q], out[HS::N];
-        load_node_d<ST, LS>(A.self, copy, i, j, A.rho_shift, fs);
+        load_node_d<ST, LS>(A.self, copy, i, j, sh_of(A), fs);
         project_col<LS, HS>(fs, tq, out, rho, ux, uy, cl6);
 #pragma unroll
         for (int tp = 0; tp < HS::N; ++tp)
-            emit_pop<ST, HS>(A.other, copy, i, j, A.rho_shift, tp + HS::N * tq, out[tp], rho, ux, uy, A.g, A.ph);
+            emit_pop<ST, HS>(A.other, copy, i, j, sh_of(A), tp + HS::N * tq, out[tp], rho, ux, uy, A.g, A.ph);
     } else {
         double fs[HS::Q], out[LS::N];
-        load_node_d<ST, HS>(A.other, copy, i, j, A.rho_shift, fs);
+        load_node_d<ST, HS>(A.other, copy, i, j, sh_of(A), fs);
         project_col<HS, LS>(fs, tq, out, rho, ux, uy);
 #pragma unroll
         for (int tp = 0; tp < LS::N; ++tp)
-            emit_pop<ST, LS>(A.self, copy, i, j, A.rho_shift, tp + LS::N * tq, out[tp], rho, ux, uy, A.g, A.ph);
+            emit_pop<ST, LS>(A.self, copy, i, j, sh_of(A), tp + LS::N * tq, out[tp], rho, ux, uy, A.g, A.ph);
     }
 }
 
@@ -1730,7 +1778,7 @@ __global__ __launch_bounds__(64) void k_closure_infer(const StepArgs A) {
                 const int e = e0 + lane;
                 const int i = A.items[2 * e], j = A.items[2 * e + 1];
                 double f9[9];
-                load_node_d<ST, LS>(A.self, A.cur ^ 1, i, j, A.rho_shift, f9);
+                load_node_d<ST, LS>(A.self, A.cur ^ 1, i, j, sh_of(A), f9);
                 closure_inputs<LS>(A.cn, f9, A.ph.rho_ref, xs[lane], rs[lane]);
             } else {
 #pragma unroll
@@ -1769,10 +1817,10 @@ __global__ __launch_bounds__(64) void k_closure_flags(const NodeArgs A) {
                 double f9[9];
                 if (region_at(i, j, A.g) == REG_HIGH) {
                     double f36[36];
-                    load_node_d<ST, HS>(A.other, A.cur, i, j, A.rho_shift, f36);
+                    load_node_d<ST, HS>(A.other, A.cur, i, j, sh_of(A), f36);
                     project_d<HS, LS>(f36, f9, nullptr);
                 } else {
-                    load_node_d<ST, LS>(A.self, A.cur, i, j, A.rho_shift, f9);
+                    load_node_d<ST, LS>(A.self, A.cur, i, j, sh_of(A), f9);
                 }
                 closure_inputs<LS>(A.cn, f9, A.ph.rho_ref, xs[lane], rs[lane]);
             } else {
@@ -1806,7 +1854,7 @@ __global__ void k_closure_samples(const NodeArgs A) {
         const int j = n / A.g.nx, i = n - j * A.g.nx;
         using TH = typename HS::T;
         double f36[36], f9[9];
-        load_node_d<ST, HS>(A.self, A.cur, i, j, A.rho_shift, f36);
+        load_node_d<ST, HS>(A.self, A.cur, i, j, sh_of(A), f36);
         project_d<HS, LS>(f36, f9, nullptr);
         double a[6][6];
 #pragma unroll
@@ -1868,11 +1916,11 @@ __global__ void k_refresh(const NodeArgs A) {
     int r = region_at(i, j, A.g);
     if (!owns(r, A.self_high)) return;
     double f[SS::Q];
-    load_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+    load_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), f);
     int t = tile_of(i, A.g);
     bool proj = (OO::Q > 0) && A.g.iface == IF_HERMITE &&
                 neighbour_in(i, j, A.self_high ? REG_LOW : REG_HIGH, A.g.blo[t], A.g.bhi[t], A.g);
-    finish_node<ST, SS, OO>(A.self, A.other, A.cur, i, j, A.rho_shift, f, false, proj, A.g, A.ph);
+    finish_node<ST, SS, OO>(A.self, A.other, A.cur, i, j, sh_of(A), f, false, proj, A.g, A.ph);
 }
 
 // f = f_eq(rho, u) on the nodes of this set (in0..2 = rho, ux, uy fields)
@@ -1885,7 +1933,7 @@ __global__ void k_init_eq(const NodeArgs A) {
     int n = j * A.g.nx + i;
     double f[SS::Q];
     feq_d<SS>(A.in0[n], A.in1[n], A.in2[n], f);
-    store_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+    store_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), f);
 }
 
 // populations from an FP64 [Q][nrow][nx] array (own nodes and, for the low
@@ -1901,7 +1949,7 @@ __global__ void k_set_pop(const NodeArgs A) {
     double f[SS::Q];
 #pragma unroll
     for (int a = 0; a < SS::Q; ++a) f[a] = A.in0[a * NN + j * A.g.nx + i];
-    store_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+    store_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), f);
 }
 
 template <class ST, class SS, class OO>
@@ -1912,7 +1960,7 @@ __global__ void k_get_pop(const NodeArgs A) {
     const int64_t NN = (int64_t)A.g.nrow * A.g.nx;
     double f[SS::Q];
     if (owns(r, A.self_high) || r == REG_IFACE) {
-        load_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+        load_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), f);
     } else {
 #pragma unroll
         for (int a = 0; a < SS::Q; ++a) f[a] = __builtin_nan("");
@@ -1930,7 +1978,7 @@ __global__ void k_moments(const NodeArgs A) {
     int r = region_at(i, j, A.g);
     if (!(owns(r, A.self_high) || (!A.self_high && r == REG_IFACE))) return;
     double f[SS::Q], rho, ux, uy;
-    load_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+    load_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), f);
     moments_d<SS>(f, rho, ux, uy);
     int n = j * A.g.nx + i;
     A.out0[n] = rho;
@@ -1949,7 +1997,7 @@ __global__ void k_indicator(const NodeArgs A) {
     using TB = typename SS::T;
     constexpr int N = SS::N;
     double f[SS::Q];
-    load_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, f);
+    load_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), f);
     double a00 = 0, a10 = 0, a01 = 0, a20 = 0, a11 = 0, a02 = 0;
 #pragma unroll
     for (int a = 0; a < SS::Q; ++a) {
@@ -1982,7 +2030,7 @@ __global__ void k_convert(const NodeArgs A) {
         int r0 = reg_of(A.oblo[t], A.obhi[t], j, A.g);
         if (!owns(r0, !A.self_high)) return;
         double fo[OO::Q], fs[SS::Q];
-        load_node_d<ST, OO>(A.other, A.cur, i, j, A.rho_shift, fo);
+        load_node_d<ST, OO>(A.other, A.cur, i, j, sh_of(A), fo);
         const double *cl = nullptr;
         if (A.closure && A.self_high) cl = A.closure + (int64_t)(j * A.g.nx + i) * SS::Q;
         double cl36[SS::Q];
@@ -2004,7 +2052,7 @@ __global__ void k_convert(const NodeArgs A) {
             }
         }
         project_d<OO, SS>(fo, fs, cl);
-        store_node_d<ST, SS>(A.self, A.cur, i, j, A.rho_shift, fs);
+        store_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), fs);
     }
 }
 
@@ -2038,8 +2086,8 @@ __global__ void k_paper_iface(const NodeArgs A, int copy, int recompute) {
     double fL[LS::Q], fH[HS::Q];
     if (recompute) {
         double fl[LS::Q], fh[HS::Q], e1[HS::Q > LS::Q ? HS::Q : LS::Q], e2[HS::Q > LS::Q ? HS::Q : LS::Q];
-        load_node_d<ST, LS>(BL, copy, i, jl, A.rho_shift, fl);
-        load_node_d<ST, HS>(BH, copy, i, jh, A.rho_shift, fh);
+        load_node_d<ST, LS>(BL, copy, i, jl, sh_of(A), fl);
+        load_node_d<ST, HS>(BH, copy, i, jh, sh_of(A), fh);
         double rl, uxl, uyl, rh, uxh, uyh;
         moments_d<LS>(fl, rl, uxl, uyl);
         moments_d<HS>(fh, rh, uxh, uyh);
@@ -2053,14 +2101,14 @@ __global__ void k_paper_iface(const NodeArgs A, int copy, int recompute) {
 #pragma unroll
         for (int a = 0; a < HS::Q; ++a) fH[a] = e1[a] + (fh[a] - e2[a]);
     } else {
-        load_node_d<ST, LS>(BL, copy, i, jI, A.rho_shift, fL);
-        load_node_d<ST, HS>(BH, copy, i, jI, A.rho_shift, fH);
+        load_node_d<ST, LS>(BL, copy, i, jI, sh_of(A), fL);
+        load_node_d<ST, HS>(BH, copy, i, jI, sh_of(A), fH);
     }
     // I row in both sets, plus the copy beyond I on the opposite side
-    emit_node<ST, LS>(BL, copy, i, jI, A.rho_shift, fL, true, A.g, A.ph);
-    emit_node<ST, LS>(BL, copy, i, jh, A.rho_shift, fL, true, A.g, A.ph);
-    emit_node<ST, HS>(BH, copy, i, jI, A.rho_shift, fH, true, A.g, A.ph);
-    emit_node<ST, HS>(BH, copy, i, jl, A.rho_shift, fH, true, A.g, A.ph);
+    emit_node<ST, LS>(BL, copy, i, jI, sh_of(A), fL, true, A.g, A.ph);
+    emit_node<ST, LS>(BL, copy, i, jh, sh_of(A), fL, true, A.g, A.ph);
+    emit_node<ST, HS>(BH, copy, i, jI, sh_of(A), fH, true, A.g, A.ph);
+    emit_node<ST, HS>(BH, copy, i, jl, sh_of(A), fH, true, A.g, A.ph);
 }
 
 // Batched FP64 projection (test hook / closure training): n nodes, [node][Q]

@@ -290,7 +290,7 @@ struct lb_lattice {
     const lbk::KernelSet *ks[2];
     Geo geo;
     Phys ph;
-    double dt, tau0, rho_shift;
+    double dt, tau0, rho_shift, dshift;   // storage shift s0, ds (lbi::Shift)
     int ntiles, tile_w, cur;
     int64_t step;
     bool initialized;
@@ -333,6 +333,7 @@ NodeArgs node_args(const lb_lattice *L, int s, int copy) {
     a.self = L->buf[s];
     a.other = L->buf[1 - s];
     a.rho_shift = L->rho_shift;
+    a.dshift = L->dshift;
     a.cur = copy;
     a.self_high = s;
     a.which = s;
@@ -561,6 +562,7 @@ lb_status one_step(lb_lattice *L) {
     a.g = L->geo;
     a.ph = L->ph;
     a.rho_shift = L->rho_shift;
+    a.dshift = L->dshift;
     a.cur = L->cur;
     a.seed = step_seed(L->step);
     const bool par = L->concurrent && !L->timing && L->nitems[0] && L->nitems[1] && L->p.iface == LB_IFACE_HERMITE;
@@ -784,7 +786,17 @@ lb_status lb_create_lattice(const lb_params *p, void *dev_workspace, size_t byte
     const double xm = std::max(xmax_of(L->n[0]), xmax_of(L->n[1]));
     L->dt = p->dt > 0 ? p->dt : p->cfl * (1.0 / xm);
     L->tau0 = p->kn * p->ny;
+    // storage reference (lbi::Shift): 0 for FP64; rho_ref for FP32 / BF16,
+    // or, for a pressure-driven lattice, the imposed linear density ramp at
+    // the centre of each group of SHIFT_GROUP columns, so that the stored
+    // deviations carry no density ramp
     L->rho_shift = p->storage == LB_STORE_F64 ? 0.0 : p->rho_ref;
+    L->dshift = 0.0;
+    if (p->storage != LB_STORE_F64 && p->xbc == LB_XBC_PRESSURE && p->rho_in != p->rho_out) {
+        const double slope = (p->rho_out - p->rho_in) / double(p->nx - 1);
+        L->rho_shift = p->rho_in + slope * 0.5 * double(lbi::SHIFT_GROUP - 1);
+        L->dshift = slope * double(lbi::SHIFT_GROUP);
+    }
     L->tile_w = p->tile_w > 0 ? p->tile_w : p->nx;
     L->ntiles = ntiles_of(*p);
     for (int s = 0; s < 2; ++s) {
@@ -1220,6 +1232,7 @@ lb_status lb_change_regions(lb_lattice *L, const int32_t *lo, const int32_t *hi)
         a.g = L->geo;
         a.ph = L->ph;
         a.rho_shift = L->rho_shift;
+        a.dshift = L->dshift;
         a.cur = L->cur ^ 1;   // the kernels act on copy cur ^ 1
         a.self = L->buf[0];
         a.other = L->buf[1];
@@ -1851,6 +1864,7 @@ lb_status lb_batch_create(lb_lattice *const *lattices, int32_t n, void *hip_stre
             a.g = L->geo;
             a.ph = L->ph;
             a.rho_shift = L->rho_shift;
+            a.dshift = L->dshift;
             a.self = L->buf[s];
             a.other = L->buf[1 - s];
             a.ks = L->kconst[s];

@@ -444,13 +444,13 @@ def _c3_storage_error(oracle, lb, storage):
     return rel_u(uxg, uyg, uxo, uyo)
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("bf16", 5e-2)])
-def test_pressure_channel_storage_error(oracle, lb, storage, tol):
+def test_pressure_channel_storage_error(oracle, lb):
     # pressure-driven channel (density 2 -> 1, Courant 0.3), fixed bands,
-    # reduced-precision storage against the FP64 oracle
-    err = _c3_storage_error(oracle, lb, storage)
-    print(f"{storage}: relative velocity error vs FP64 oracle after 300 steps = {err:.3e}")
-    assert err < tol
+    # FP32 storage (referenced to the imposed density ramp per column
+    # group) against the FP64 oracle: the 1e-5 goal
+    err = _c3_storage_error(oracle, lb, "f32")
+    print(f"f32: relative velocity error vs FP64 oracle after 300 steps = {err:.3e}")
+    assert err < 1e-5
 
 
 def _c2_velocity(lb, storage, steps):
@@ -465,8 +465,7 @@ def _c2_velocity(lb, storage, steps):
     return ux, uy
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("bf16", 1e-2)])
-def test_poiseuille_c2_storage_error(lb, storage, tol):
+def _c2_storage_error(lb, storage):
     # the full body-force channel (1024 x 513, 10k steps, Courant 0.5) in
     # reduced precision against the same run with FP64 storage (which the
     # coupled parity tests tie to the oracle at 1e-10)
@@ -475,13 +474,32 @@ def test_poiseuille_c2_storage_error(lb, storage, tol):
     u = _c2_velocity(lb, storage, c["steps"])
     err = rel_u(u[0], u[1], ref[0], ref[1])
     print(f"{storage}: relative velocity error vs FP64 after {c['steps']} steps = {err:.3e}")
-    assert err < tol
+    return err
 
 
-@pytest.mark.xfail(strict=True, reason="bf16 storage misses the 2e-3 velocity-error goal (measured 5e-3 on the "
-                                       "body-force channel, 2e-2 on the pressure channel)")
-def test_bf16_storage_goal(oracle, lb):
-    assert _c3_storage_error(oracle, lb, "bf16") < BF16_GOAL
+def test_poiseuille_c2_storage_error(lb):
+    # FP32 storage: the 1e-5 goal
+    assert _c2_storage_error(lb, "f32") < 1e-5
+
+
+# bf16 storage: the 2e-3 goal is missed on both channels (measured 5.1e-3 on
+# the body-force channel after 10k steps, 9.1e-3 on the pressure channel
+# after 300): an 8-bit significand on the stored deviations, whose velocity
+# part w xi u rho it must resolve.  These strict expected failures are the
+# bf16 result; they turn into failures if the goal is ever met.
+@pytest.mark.xfail(strict=True, reason="bf16 storage misses the 2e-3 velocity-error goal")
+@pytest.mark.parametrize("case", ["pressure_channel", "poiseuille_c2"])
+def test_bf16_storage_goal(oracle, lb, case):
+    err = _c3_storage_error(oracle, lb, "bf16") if case == "pressure_channel" else _c2_storage_error(lb, "bf16")
+    print(f"bf16 {case}: relative velocity error {err:.3e} (goal {BF16_GOAL})")
+    assert err < BF16_GOAL
+
+
+def test_bf16_storage_regression_bound(oracle, lb):
+    # not the goal (see above): a guard that the stochastic rounding keeps
+    # bf16 near its measured error (slow flows stall with round-to-nearest,
+    # error 0.95)
+    assert _c3_storage_error(oracle, lb, "bf16") < 2e-2
 
 
 # ---------------------------------------------- execution modes, same bits
