@@ -46,6 +46,12 @@
 #ifndef LB_PAIR_SPLIT36
 #define LB_PAIR_SPLIT36 2
 #endif
+// row offset in the vector offset of every buffer access (the scalar offset
+// then holds the population plane alone, loop-invariant), or in the scalar
+// offset for wide items
+#ifndef LB_ROWV
+#define LB_ROWV 1
+#endif
 // the batch update of every set in one launch: waves per D2Q36 and D2Q16
 // item, and the occupancy it is compiled for
 #ifndef LB_MULTI_SPLIT36
@@ -847,8 +853,8 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
 #define LB_SOFF(a, j) unsigned(((int64_t)(a) * P + rb + (int64_t)((j) + 2) * pitch) * EB)
     // narrow lattices: the row is per lane, so it moves into the vector
     // offset and the scalar offset keeps the population only
-#define LB_VO(v, j) (NW ? (v) + unsigned((int64_t)((j) + 2) * pitch * EB) : (v))
-#define LB_SO(a, j) (NW ? unsigned(((int64_t)(a) * P + rb) * EB) : LB_SOFF(a, j))
+#define LB_VO(v, j) ((NW || LB_ROWV) ? (v) + unsigned((int64_t)((j) + 2) * pitch * EB) : (v))
+#define LB_SO(a, j) ((NW || LB_ROWV) ? unsigned(((int64_t)(a) * P + rb) * EB) : LB_SOFF(a, j))
 
     // region ownership of this lane's column (bands of its tile)
     const int tl = tile_of(min(max(col, 0), nx - 1), g);
