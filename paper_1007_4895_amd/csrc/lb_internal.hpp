@@ -59,8 +59,6 @@ constexpr int SHIFT_GROUP = 60;
 struct Shift {
     double s0, ds;
 };
-__host__ __device__ inline int shift_group(int i) { return i >= 0 ? i / SHIFT_GROUP : (i - (SHIFT_GROUP - 1)) / SHIFT_GROUP; }
-__host__ __device__ inline double shift_at(const Shift &s, int i) { return s.s0 + s.ds * double(shift_group(i)); }
 
 // Per-set kernel constants, in double and float: nu_p = x_p dt and
 // k_p = |nu_p| (1 - |nu_p|) / 2 for the p-th 1D abscissa.

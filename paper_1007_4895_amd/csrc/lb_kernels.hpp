@@ -428,6 +428,12 @@ __device__ __forceinline__ typename ST::S *plane0(const Buf &b, int copy) {
     return reinterpret_cast<typename ST::S *>(b.base[copy]) + b.rowbase;
 }
 
+// storage reference of column i (Shift): s0 + ds * floor(i / SHIFT_GROUP)
+__device__ __forceinline__ int shift_group(int i) {
+    return i >= 0 ? i / SHIFT_GROUP : (i - (SHIFT_GROUP - 1)) / SHIFT_GROUP;
+}
+__device__ __forceinline__ double shift_at(const Shift &s, int i) { return s.s0 + s.ds * double(shift_group(i)); }
+
 template <class A>
 __device__ __forceinline__ Shift sh_of(const A &a) { return Shift{a.rho_shift, a.dshift}; }
 
