@@ -54,6 +54,16 @@ def _declare(L):
     L.lbo_gh_rule.argtypes = [C.c_int, _dp, _dp]
     L.lbo_vset.argtypes = [C.c_int, _dp, _dp, _dp]
     L.lbo_moments_node.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
+    L.lbo_moments_node_t.argtypes = [C.c_int, _dp, _dp, _dp, _dp, _dp]
+    L.lbo_heat_flux_node.argtypes = [C.c_int, _dp, _dp, _dp]
+    L.lbo_equilibrium_t.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, _dp]
+    L.lbo_force_t.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                              C.c_double, C.c_double, _dp]
+    L.lbo_project_t.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _dp, _dp, _dp]
+    L.lbo_init_equilibrium_t.argtypes = [C.c_void_p, _dp, _dp, _dp, _dp]
+    L.lbo_thermal.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.lbo_energy.restype = C.c_double
+    L.lbo_energy.argtypes = [C.c_void_p]
     L.lbo_hermite_coeffs.argtypes = [C.c_int, _dp, _dp]
     L.lbo_from_coeffs.argtypes = [C.c_int, _dp, _dp]
     L.lbo_equilibrium.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, _dp]
@@ -125,6 +135,22 @@ def moments(n: int, f):
     return r.value, ux.value, uy.value
 
 
+def moments_t(n: int, f):
+    """rho, ux, uy and the temperature T from sum xi^2 f = rho (u^2 + 2 T)."""
+    f = _f64(f)
+    r, ux, uy, T = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    lib().lbo_moments_node_t(n, _d(f), C.byref(r), C.byref(ux), C.byref(uy), C.byref(T))
+    return r.value, ux.value, uy.value, T.value
+
+
+def heat_flux(n: int, f):
+    """q = 1/2 sum (xi - u) |xi - u|^2 f of one node."""
+    f = _f64(f)
+    qx, qy = C.c_double(), C.c_double()
+    lib().lbo_heat_flux_node(n, _d(f), C.byref(qx), C.byref(qy))
+    return qx.value, qy.value
+
+
 def hermite_coeffs(n: int, f):
     """a[k, m] = sum_alpha f He_k(xi_x) He_m(xi_y) (Eq. an, component form)."""
     f = _f64(f)
@@ -140,26 +166,35 @@ def from_coeffs(n: int, a):
     return f
 
 
-def equilibrium(n: int, order: int, rho, ux, uy):
-    """Order-N Hermite equilibrium, Eq. (approxfeq) with T = 1."""
+def equilibrium(n: int, order: int, rho, ux, uy, T=None):
+    """Order-N Hermite equilibrium, Eq. (approxfeq); T = None is the
+    isothermal form (T = 1)."""
     f = np.zeros(n * n)
-    lib().lbo_equilibrium(n, order, rho, ux, uy, _d(f))
+    if T is None:
+        lib().lbo_equilibrium(n, order, rho, ux, uy, _d(f))
+    else:
+        lib().lbo_equilibrium_t(n, order, rho, ux, uy, T, _d(f))
     return f
 
 
-def force(n: int, order: int, rho, ux, uy, gx, gy):
+def force(n: int, order: int, rho, ux, uy, gx, gy, T=None):
     """Hermite body-force term g_alpha up to order N (Sec. 2.1)."""
     g = np.zeros(n * n)
-    lib().lbo_force(n, order, rho, ux, uy, gx, gy, _d(g))
+    if T is None:
+        lib().lbo_force(n, order, rho, ux, uy, gx, gy, _d(g))
+    else:
+        lib().lbo_force_t(n, order, rho, ux, uy, T, gx, gy, _d(g))
     return g
 
 
-def project(ns: int, ords: int, nd: int, ordd: int, fs, closure=None):
-    """Hermite-moment projection of one node's populations from set ns to nd."""
+def project(ns: int, ords: int, nd: int, ordd: int, fs, closure=None, thermal=False):
+    """Hermite-moment projection of one node's populations from set ns to nd
+    (thermal: the equilibria at the node's own temperature)."""
     fs = _f64(fs)
     fd = np.zeros(nd * nd)
     cl = None if closure is None else _d(_f64(closure))
-    lib().lbo_project(ns, ords, nd, ordd, _d(fs), cl, _d(fd))
+    fn = lib().lbo_project_t if thermal else lib().lbo_project
+    fn(ns, ords, nd, ordd, _d(fs), cl, _d(fd))
     return fd
 
 
@@ -199,13 +234,16 @@ class Lattice:
     u_osc sin(omega_osc t), t the time of the level being computed
     (oscillatory Couette flow, Sec. 3.5).  ybc=YBC_SHEAR: a wall at the
     bottom and an imposed shear rate `shear` above the top row (Kramers'
-    problem, Sec. 3.3)."""
+    problem, Sec. 3.3).  thermal=True: every node's temperature comes from
+    its energy moment and enters the equilibrium (Eq. demoeq), the
+    relaxation rate (p / mu), the interface (T_I) and the indicator (heat
+    flux); the walls are at T_wall = (bottom, top)."""
 
     def __init__(self, nx, ny, *, kn, n_low=3, n_high=3, eq_low=2, eq_high=None,
                  force_low=None, force_high=None, dt=None, rho_ref=1.0, tau_mode=TAU_CONST,
                  gx=0.0, gy=0.0, u_wall=((0.0, 0.0), (0.0, 0.0)), xbc=XBC_PERIODIC,
                  ybc=YBC_WALLS, rho_in=1.0, rho_out=1.0, iface=IFACE_HERMITE, tile_w=None,
-                 u_osc=0.0, omega_osc=0.0, shear=0.0):
+                 u_osc=0.0, omega_osc=0.0, shear=0.0, thermal=False, T_wall=(1.0, 1.0)):
         eq_high = eq_low if eq_high is None else eq_high
         force_low = eq_low if force_low is None else force_low
         force_high = eq_high if force_high is None else force_high
@@ -219,9 +257,11 @@ class Lattice:
         self.tile_w = tile_w
         self.ntiles = (nx + tile_w - 1) // tile_w
         dp = np.array([kn, rho_ref, dt, gx, gy, u_wall[0][0], u_wall[0][1], u_wall[1][0],
-                       u_wall[1][1], rho_in, rho_out, u_osc, omega_osc, shear], dtype=np.float64)
+                       u_wall[1][1], rho_in, rho_out, u_osc, omega_osc, shear,
+                       T_wall[0], T_wall[1]], dtype=np.float64)
         ip = np.array([nx, ny, n_low, n_high, eq_low, eq_high, force_low, force_high,
-                       tau_mode, xbc, ybc, iface, tile_w], dtype=np.int32)
+                       tau_mode, xbc, ybc, iface, tile_w, int(bool(thermal))], dtype=np.int32)
+        self.thermal = bool(thermal)
         self._h = lib().lbo_create(_d(dp), _i(ip))
         if not self._h:
             raise ValueError("oracle lattice creation failed")
@@ -255,16 +295,17 @@ class Lattice:
                 r[j, i] = lib().lbo_region(self._h, i, j)
         return r
 
-    def init_equilibrium(self, rho=None, ux=None, uy=None):
+    def init_equilibrium(self, rho=None, ux=None, uy=None, T=None):
+        """Equilibrium start; T (thermal lattices) defaults to 1."""
         args = []
-        for a in (rho, ux, uy):
+        for a in (rho, ux, uy, T):
             if a is None:
                 args.append(None)
             else:
                 a = _f64(np.broadcast_to(a, (self.nrow, self.nx)))
                 args.append(a)
         ptrs = [None if a is None else _d(a) for a in args]
-        lib().lbo_init_equilibrium(self._h, *ptrs)
+        lib().lbo_init_equilibrium_t(self._h, *ptrs)
 
     def set_populations(self, which, f):
         f = _f64(f)
@@ -301,6 +342,17 @@ class Lattice:
         out = np.zeros(3)
         lib().lbo_conservation(self._h, _d(out))
         return out
+
+    def thermal_moments(self):
+        """Temperature and heat flux (qx, qy) of every node, [ny+1][nx]."""
+        shp = (self.nrow, self.nx)
+        T, qx, qy = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+        lib().lbo_thermal(self._h, _d(T), _d(qx), _d(qy))
+        return T, qx, qy
+
+    def energy(self):
+        """Total energy, the sum over nodes of 1/2 sum |xi|^2 f."""
+        return float(lib().lbo_energy(self._h))
 
     def indicator(self):
         B = np.zeros((self.nrow, self.nx))
