@@ -13,7 +13,9 @@
  *    or aborts across the ABI.  lb_last_error() returns a thread-local text
  *    for the last failure.
  *  - Units: grid spacing 1; velocities in units of sqrt(R T0), so the
- *    Gauss-Hermite abscissae are the particle speeds; T = 1.  Node rows are
+ *    Gauss-Hermite abscissae are the particle speeds; temperatures in units
+ *    of T0.  Isothermal lattices (the default) fix T = 1; thermal lattices
+ *    (lb_params.thermal) take each node's T from its energy moment.  Node rows are
  *    j = 0..ny (ny + 1 rows); with walls, rows 0 and ny are the wall nodes and
  *    the channel height ny is the length of Eq. (KN): the relaxation time at
  *    density rho_ref is kn * ny.
@@ -82,6 +84,21 @@ typedef struct lb_params {
                                   u_osc sin(omega_osc t), with t = (n + 1) dt when
                                   step n -> n + 1 applies the wall condition */
     double shear_top;          /* LB_YBC_SHEAR: imposed du/dy above the top row */
+    /* Thermal lattice (the non-isothermal form of Eq. (demoeq), Sec. 3.2 and
+     * Sec. 2.2): thermal != 0 takes every node's temperature from its energy
+     * moment, sum xi^2 f = rho (u^2 + 2 T), and uses it in the equilibrium's
+     * Hermite coefficients (the Maxwellian's, to the set's order), in the
+     * force, in the relaxation rate of LB_TAU_RHO (collision frequency p / mu
+     * with p = rho T: tau = kn ny rho_ref / (rho T)), in the pressure and
+     * shear ghost nodes (the edge node's T), in the interface (T_I, the
+     * neighbours' average, LB_IFACE_PAPER; the projection's equilibria at
+     * the node's T, LB_IFACE_HERMITE) and in the indicator (heat flux).
+     * The diffuse walls emit S(T_wall, u_wall).  Built for FP64 and FP32
+     * storage; not for batches or the learned closure.  Ignored when
+     * thermal == 0 (T = 1 everywhere, walls included). */
+    double T_wall[2];          /* bottom, top wall temperature (> 0) */
+    int32_t thermal;           /* 0 = isothermal (default), 1 = thermal */
+    int32_t reserved_;         /* 0 */
 } lb_params;
 
 typedef struct lb_lattice lb_lattice;
@@ -90,7 +107,8 @@ typedef struct lb_lattice lb_lattice;
 const char *lb_last_error(void);
 
 /* Fill p with defaults: D2Q9 everywhere, eq order 2, HERMITE interface,
- * F64 storage, walls, periodic x, kn = 0.1, rho_ref = 1, cfl = 0.5. */
+ * F64 storage, walls, periodic x, kn = 0.1, rho_ref = 1, cfl = 0.5,
+ * isothermal, wall temperatures 1. */
 lb_status lb_params_default(lb_params *p);
 
 /* Device workspace needed for a lattice with parameters p (0 on invalid p). */
@@ -123,6 +141,12 @@ lb_status lb_get_regions(const lb_lattice *L, int32_t *band_lo, int32_t *band_hi
 /* Equilibrium start (Eq. approxfeq) from host fields; NULL = rho_ref / 0. */
 lb_status lb_init_equilibrium(lb_lattice *L, const double *rho, const double *ux, const double *uy);
 
+/* The same with a temperature field T (host [ny+1][nx], NULL = 1): the
+ * Maxwellian's Hermite expansion at (rho, u, T) to each set's order.
+ * LB_EINVAL on an isothermal lattice when T is given. */
+lb_status lb_init_equilibrium_thermal(lb_lattice *L, const double *rho, const double *ux, const double *uy,
+                                      const double *T);
+
 /* Advance nsteps time steps (Sec. 3.1 update, Sec. 3.2 walls, Sec. 2.2
  * interface).  Asynchronous on the lattice stream.  With an oscillating
  * bottom wall, the host recomputes that wall's equilibrium sums for every
@@ -138,6 +162,18 @@ lb_status lb_moments(lb_lattice *L, double *rho, double *ux, double *uy, int32_t
  * in a fixed order (deterministic).  Waits.  LB_EUNSTABLE if not finite. */
 lb_status lb_conservation(lb_lattice *L, double out[3]);
 
+/* Temperature T = (sum xi^2 f / rho - u^2) / 2 and heat flux
+ * q = 1/2 sum (xi - u) |xi - u|^2 f of every node ([ny+1][nx], FP64; the
+ * heat flux of the 'B' parameter of Sec. 2.2).  Any lattice (an isothermal
+ * one reports the temperature its populations carry).  on_device as for
+ * lb_moments. */
+lb_status lb_thermal_moments(lb_lattice *L, double *T, double *qx, double *qy, int32_t on_device);
+
+/* *out = total energy, the sum over all nodes of 1/2 sum_alpha xi_alpha^2
+ * f_alpha, reduced like lb_conservation (deterministic).  Waits.
+ * Conserved by the update of a periodic thermal lattice. */
+lb_status lb_energy(lb_lattice *L, double *out);
+
 /* Populations of set which (0 = low, 1 = high) as FP64 host arrays
  * [Q][ny+1][nx].  get: nodes not evolved in that set (and not interface
  * rows) read as NaN.  set: only those nodes are read; the ghost, image and
@@ -152,9 +188,11 @@ lb_status lb_get_state(lb_lattice *L, void *host, size_t bytes);
 lb_status lb_set_state(lb_lattice *L, const void *host, size_t bytes);
 int64_t lb_step_count(const lb_lattice *L);
 
-/* Non-equilibrium indicator per node (an isothermal form of the 'B'
- * breakdown parameter of Sec. 2.2: max over the second-order Hermite
- * components of |a_km - rho ux^k uy^m| / rho), FP64 [ny+1][nx]. */
+/* Non-equilibrium indicator per node (the 'B' breakdown parameter of
+ * Sec. 2.2 made dimensionless), FP64 [ny+1][nx].  Isothermal lattices: max
+ * over the second-order Hermite components of |a_km - rho ux^k uy^m| / rho.
+ * Thermal lattices: max of |P_ij - p delta_ij| / p (ij = xx, xy, yy;
+ * P_ij = sum c_i c_j f, c = xi - u, p = rho T) and |q_i| / (p sqrt(T)). */
 lb_status lb_indicator(lb_lattice *L, double *B, int32_t on_device);
 
 /* Re-decompose from the indicator: per tile, the bottom band reaches one row

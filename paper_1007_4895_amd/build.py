@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblb.so")
-SOURCES = ["lb_runtime.hip", "lb_inst_f64.hip", "lb_inst_f32.hip", "lb_inst_bf16.hip", "lb_mlp.hip"]
+SOURCES = ["lb_runtime.hip", "lb_inst_f64.hip", "lb_inst_f32.hip", "lb_inst_bf16.hip", "lb_inst_thermal_f64.hip",
+           "lb_inst_thermal_f32.hip", "lb_mlp.hip"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

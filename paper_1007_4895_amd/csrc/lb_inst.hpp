@@ -97,6 +97,9 @@ struct Inst {
     static void indicator(const NodeArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_indicator<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
     }
+    static void thermal(const NodeArgs &a, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((k_thermal<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
+    }
     static void convert(const NodeArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_convert<ST, S, O>), dim3(grid), dim3(256), 0, s, a);
     }
@@ -114,6 +117,7 @@ struct Inst {
         k.eqS = S::EQ;
         k.nO = O::N;
         k.eqO = O::EQ;
+        k.th = S::TH ? 1 : 0;
         k.update = &update;
         k.update_timed = &update_timed;
         k.finish = &finish;
@@ -125,6 +129,7 @@ struct Inst {
         k.get_pop = &get_pop;
         k.moments = &moments;
         k.indicator = &indicator;
+        k.thermal = &thermal;
         k.convert = &convert;
         k.paper_iface = &paper_iface;
         k.project = &project;
@@ -161,3 +166,5 @@ struct MultiInst {
 #define LB_MULTI(ST, e6, e4) lbk::MultiInst<ST, e6, e4>::make()
 #define LB_PAIR(ST, SID, n1, e1, n2, e2) \
     lbk::Inst<ST, lbt::VSet<n1, e1>, lbt::VSet<n2, e2>>::make(SID)
+#define LB_PAIR_TH(ST, SID, n1, e1, n2, e2) \
+    lbk::Inst<ST, lbt::VSet<n1, e1, true>, lbt::VSet<n2, e2, true>>::make(SID)

@@ -65,7 +65,7 @@ struct Shift {
 struct SetK {
     double nu[8], kk[8];
     float nuf[8], kkf[8];
-    // diffuse walls [bottom, top]: S' = f_eq(1, u_wall) - w per population,
+    // diffuse walls [bottom, top]: S' = f_eq(1, u_wall, T_wall) - w per population,
     // K = sum_leaving |xi_y| w, D' = sum_leaving |xi_y| S'
     double sp[2][36], wK[2], wD[2];
     float spf[2][36], wKf[2], wDf[2];
@@ -155,8 +155,9 @@ struct NodeArgs {
     int32_t cur;
     int32_t self_high;
     int32_t which;       // set index of `self` in the caller's numbering
-    int32_t pad;
+    int32_t mode;        // kernel-specific variant (k_thermal: 1 = energy density)
     const double *in0, *in1, *in2;   // device FP64 inputs (fields or populations)
+    const double *in3;               // device FP64 temperature field (thermal initialisation), or NULL
     double *out0, *out1, *out2;      // device FP64 outputs
     const int32_t *oblo, *obhi;      // previous bands (region change)
     const double *closure;           // optional closure coefficients (lift)

@@ -312,18 +312,48 @@ __device__ void moments_d(const double *f, double &rho, double &ux, double &uy) 
     uy = jy / r;
 }
 
-// Order-EQ Hermite equilibrium (Eq. approxfeq, T = 1), absolute values
+// Hermite coefficients of the 1D Maxwellian factor at velocity u and
+// temperature 1 + th, h_0 .. h_{K-1}: h_0 = 1, h_1 = u,
+// h_{k+1} = u h_k + k th h_{k-1} (the three-term recurrence of He_k carried
+// over to the Gaussian's moments); isothermal sets (TH false) take
+// th = 0, h_k = u^k.
+template <bool TH, int K, class T>
+__device__ __forceinline__ void hcoef(T u, T th, T (&h)[K]) {
+    h[0] = T(1);
+#pragma unroll
+    for (int k = 1; k < K; ++k) {
+        if constexpr (TH) h[k] = k >= 2 ? u * h[k - 1] + T(k - 1) * th * h[k - 2] : h[k - 1] * u;
+        else h[k] = h[k - 1] * u;
+    }
+}
+
+// rho, u and th = T - 1 of absolute populations: T from the energy moment,
+// sum xi^2 f = rho (u^2 + 2 T), on thermal sets; th = 0 otherwise
 template <class SS>
-__device__ void feq_d(double rho, double ux, double uy, double *out) {
+__device__ void moments_td(const double *f, double &rho, double &ux, double &uy, double &th) {
+    moments_d<SS>(f, rho, ux, uy);
+    th = 0.0;
+    if constexpr (SS::TH) {
+        using TB = typename SS::T;
+        double e = 0.0;
+#pragma unroll
+        for (int a = 0; a < SS::Q; ++a) {
+            const double x = TB::rule.x[a % SS::N], y = TB::rule.x[a / SS::N];
+            e += (x * x + y * y) * f[a];
+        }
+        th = 0.5 * (e / rho - (ux * ux + uy * uy)) - 1.0;
+    }
+}
+
+// Order-EQ Hermite equilibrium (Eq. approxfeq) at temperature 1 + th (th
+// ignored unless SS is thermal), absolute values
+template <class SS>
+__device__ void feq_d(double rho, double ux, double uy, double th, double *out) {
     using TB = typename SS::T;
     constexpr int N = SS::N, EQ = SS::EQ;
     double px[EQ + 1], py[EQ + 1];
-    px[0] = py[0] = 1.0;
-#pragma unroll
-    for (int k = 1; k <= EQ; ++k) {
-        px[k] = px[k - 1] * ux;
-        py[k] = py[k - 1] * uy;
-    }
+    hcoef<SS::TH>(ux, th, px);
+    hcoef<SS::TH>(uy, th, py);
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         double B[EQ + 1];
@@ -379,13 +409,11 @@ __device__ void project_d(const double *fs, double *fd, const double *closure) {
                 a[k][m] = s;
             }
         const double rho = a[0][0], ux = a[1][0] / rho, uy = a[0][1] / rho;
+        // thermal: the node's temperature from a_20 + a_02 = rho (u^2 + 2 (T - 1))
+        const double th = SS::TH ? 0.5 * ((a[2][0] + a[0][2]) / rho - (ux * ux + uy * uy)) : 0.0;
         double px[ND + 1], py[ND + 1];
-        px[0] = py[0] = 1.0;
-#pragma unroll
-        for (int k = 1; k <= ND; ++k) {
-            px[k] = px[k - 1] * ux;
-            py[k] = py[k - 1] * uy;
-        }
+        hcoef<SS::TH>(ux, th, px);
+        hcoef<SS::TH>(uy, th, py);
         double c[ND][ND];
 #pragma unroll
         for (int k = 0; k < ND; ++k)
@@ -459,7 +487,8 @@ __device__ void store_node_d(const Buf &b, int copy, int i, int j, const Shift &
 // `own`, and to every ghost entry that stands for it: the wall ghost rows
 // (Sec. 3.2: copies of the wall node), periodic images, and the pressure
 // boundary columns (equilibrium at the prescribed density with the edge
-// node's velocity plus the edge node's non-equilibrium part).
+// node's velocity and temperature plus the edge node's non-equilibrium
+// part).
 template <class ST, class SS>
 __device__ void emit_node(const Buf &b, int copy, int i, int j, const Shift &shift, const double *f, bool own,
                           const Geo &g, const Phys &ph) {
@@ -480,13 +509,13 @@ __device__ void emit_node(const Buf &b, int copy, int i, int j, const Shift &shi
         }
         if (j == g.ny) {
             // imposed shear (Kramers' problem, Sec. 3.3): equilibrium at the
-            // node's density with its velocity raised by shear * k, plus the
-            // node's non-equilibrium part
-            double rho, ux, uy, en[SS::Q], eg[SS::Q], gq[SS::Q];
-            moments_d<SS>(f, rho, ux, uy);
-            feq_d<SS>(rho, ux, uy, en);
+            // node's density (and temperature) with its velocity raised by
+            // shear * k, plus the node's non-equilibrium part
+            double rho, ux, uy, th, en[SS::Q], eg[SS::Q], gq[SS::Q];
+            moments_td<SS>(f, rho, ux, uy, th);
+            feq_d<SS>(rho, ux, uy, th, en);
             for (int k = 1; k <= 2; ++k) {
-                feq_d<SS>(rho, ux + ph.shear * double(k), uy, eg);
+                feq_d<SS>(rho, ux + ph.shear * double(k), uy, th, eg);
 #pragma unroll
                 for (int a = 0; a < SS::Q; ++a) gq[a] = eg[a] + (f[a] - en[a]);
                 store_node_d<ST, SS>(b, copy, i, g.ny + k, shift, gq);
@@ -500,10 +529,10 @@ __device__ void emit_node(const Buf &b, int copy, int i, int j, const Shift &shi
         if (i < 2) store_node_d<ST, SS>(b, copy, i + g.nx, j, shift, f);
         if (i >= g.nx - 2) store_node_d<ST, SS>(b, copy, i - g.nx, j, shift, f);
     } else if (i == 0 || i == g.nx - 1) {
-        double rho, ux, uy, eb[SS::Q], en[SS::Q], gq[SS::Q];
-        moments_d<SS>(f, rho, ux, uy);
-        feq_d<SS>(i == 0 ? ph.rho_in : ph.rho_out, ux, uy, eb);
-        feq_d<SS>(rho, ux, uy, en);
+        double rho, ux, uy, th, eb[SS::Q], en[SS::Q], gq[SS::Q];
+        moments_td<SS>(f, rho, ux, uy, th);
+        feq_d<SS>(i == 0 ? ph.rho_in : ph.rho_out, ux, uy, th, eb);
+        feq_d<SS>(rho, ux, uy, th, en);
 #pragma unroll
         for (int a = 0; a < SS::Q; ++a) gq[a] = eb[a] + (f[a] - en[a]);
         if (i == 0) {
@@ -580,6 +609,12 @@ template <class T, int N, int SPLIT>
 __device__ __forceinline__ T (*lds_wall())[N][64] {
     __shared__ T sn[2][N][64];
     return sn;
+}
+// ... and, on thermal sets, the per y-abscissa energy sums (double-buffered)
+template <class T, int N, int SPLIT>
+__device__ __forceinline__ T (*lds_energy())[N][64] {
+    __shared__ T se[2][N][64];
+    return se;
 }
 
 // occupancy the compiler must fit the update kernel into (waves per SIMD)
@@ -959,29 +994,33 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
         // sums (nq), summed over the abscissae in order like the moments
         T nacc = T(0);
 
-        // moments of the centre values: rho' = sum f (shifted), j = sum xi f.
-        // Per y-abscissa partial sums, then summed over the abscissae in
-        // order (through LDS when the populations are split over waves), so
-        // the moments do not depend on the split.
-        T sqv[NQ], sxv[NQ];
+        // moments of the centre values: rho' = sum f (shifted), j = sum xi f
+        // (thermal sets: also e' = sum |xi|^2 f, shifted).  Per y-abscissa
+        // partial sums, then summed over the abscissae in order (through LDS
+        // when the populations are split over waves), so the moments do not
+        // depend on the split.
+        T sqv[NQ], sxv[NQ], sev[NQ];
 #pragma unroll
         for (int qq = 0; qq < NQ; ++qq) {
-            T sq = T(0), sxq = T(0);
+            T sq = T(0), sxq = T(0), seq = T(0);
 #pragma unroll
             for (int p = 0; p < N; ++p) {
                 sq += c[p + N * qq];
                 sxq += T(TB::rule.x[p]) * c[p + N * qq];
+                if constexpr (SS::TH) seq += T(TB::rule.x[p] * TB::rule.x[p]) * c[p + N * qq];
             }
             sqv[qq] = sq;
             sxv[qq] = sxq;
+            sev[qq] = seq;
         }
-        T rp = T(0), jx = T(0), jy = T(0);
+        T rp = T(0), jx = T(0), jy = T(0), ep = T(0);
         if constexpr (SPLIT == 1) {
 #pragma unroll
             for (int q = 0; q < N; ++q) {
                 rp += sqv[q];
                 jx += sxv[q];
                 jy += T(TB::rule.x[q]) * sqv[q];
+                if constexpr (SS::TH) ep += sev[q] + T(TB::rule.x[q] * TB::rule.x[q]) * sqv[q];
             }
         } else {
             const int buf = NW ? jr & 1 : (j - j0) & 1;
@@ -989,6 +1028,7 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
             for (int qq = 0; qq < NQ; ++qq) {
                 sm[buf][0][q0 + qq][lane] = sqv[qq];
                 sm[buf][1][q0 + qq][lane] = sxv[qq];
+                if constexpr (SS::TH) lds_energy<T, N, SPLIT>()[buf][q0 + qq][lane] = sev[qq];
             }
             __syncthreads();
 #pragma unroll
@@ -997,21 +1037,28 @@ __device__ __forceinline__ void update_rows(const StepArgs &A, const int cur, co
                 rp += sq;
                 jx += sm[buf][1][q][lane];
                 jy += T(TB::rule.x[q]) * sq;
+                if constexpr (SS::TH)
+                    ep += lds_energy<T, N, SPLIT>()[buf][q][lane] + T(TB::rule.x[q] * TB::rule.x[q]) * sq;
             }
         }
         const T rho = rho_shift + rp;
         const T inv = T(1) / rho;
         const T ux = jx * inv, uy = jy * inv;
-        const T om = A.ph.tau_mode == TAU_RHO ? om_rho * rho : om0;
+        // thermal: T - 1 from sum |xi|^2 f - 2 rho = e' - 2 rho' (the shift
+        // s carries sum w |xi|^2 = 2 per unit density), over 2 rho, minus
+        // |u|^2 / 2
+        T th = T(0);
+        if constexpr (SS::TH) th = T(0.5) * ((ep - T(2) * rp) * inv - (ux * ux + uy * uy));
+        // collision frequency p / mu: at a fixed viscosity it follows the
+        // pressure p = rho T
+        const T om = A.ph.tau_mode == TAU_RHO ? om_rho * rho * (T(1) + th) : om0;
         const T omr = om * rho, Gx = dtT * rho * gxT, Gy = dtT * rho * gyT;
         T px[EQ + 1], py[EQ + 1];
-        px[0] = py[0] = T(1);
-#pragma unroll
-        for (int k = 1; k <= EQ; ++k) {
-            px[k] = px[k - 1] * ux;
-            py[k] = py[k - 1] * uy;
-        }
-        // C_km: relaxation + force coefficient of He_k(x) He_m(y) / (k! m!)
+        hcoef<SS::TH>(ux, th, px);
+        hcoef<SS::TH>(uy, th, py);
+        // C_km: relaxation + force coefficient of He_k(x) He_m(y) / (k! m!):
+        // the equilibrium's rho h_k(ux) h_m(uy) and the force's
+        // k gx rho h_{k-1}(ux) h_m(uy) + m gy rho h_k(ux) h_{m-1}(uy)
         T C[EQ + 1][EQ + 1];
 #pragma unroll
         for (int k = 0; k <= EQ; ++k)
@@ -1191,7 +1238,7 @@ __device__ __forceinline__ int missing_index(int k, int m) {
 // t = tp + ND tq of one target column tq; also returns rho, u of the node.
 // The node's coefficients are formed once per column.
 template <class SS, class DD>
-__device__ void project_col(const double *fs, int tq, double *out, double &rho, double &ux, double &uy,
+__device__ void project_col(const double *fs, int tq, double *out, double &rho, double &ux, double &uy, double &th,
                             const float *cl6 = nullptr) {
     using TS = typename SS::T;
     using TD = typename DD::T;
@@ -1220,17 +1267,14 @@ __device__ void project_col(const double *fs, int tq, double *out, double &rho, 
     rho = a[0][0];
     ux = a[1][0] / rho;
     uy = a[0][1] / rho;
+    th = SS::TH ? 0.5 * ((a[2][0] + a[0][2]) / rho - (ux * ux + uy * uy)) : 0.0;
     if constexpr (SS::N == DD::N && SS::EQ == DD::EQ) {
 #pragma unroll
         for (int tp = 0; tp < ND; ++tp) out[tp] = fs[tp + ND * tq];
     } else {
         double px[ND + 1], py[ND + 1];
-        px[0] = py[0] = 1.0;
-#pragma unroll
-        for (int k = 1; k <= ND; ++k) {
-            px[k] = px[k - 1] * ux;
-            py[k] = py[k - 1] * uy;
-        }
+        hcoef<SS::TH>(ux, th, px);
+        hcoef<SS::TH>(uy, th, py);
         double b[ND];
 #pragma unroll
         for (int k = 0; k < ND; ++k) {
@@ -1259,22 +1303,21 @@ __device__ void project_col(const double *fs, int tq, double *out, double &rho, 
     }
 }
 
-// one population of the order-EQ equilibrium (absolute)
+// one population of the order-EQ equilibrium (absolute), temperature 1 + th
 template <class SS>
-__device__ double feq_one(double rho, double ux, double uy, int t) {
+__device__ double feq_one(double rho, double ux, double uy, double th, int t) {
     using TB = typename SS::T;
     const int tp = t % SS::N, tq = t / SS::N;
-    double s = 0.0, pk = 1.0;
+    double px[SS::EQ + 1], py[SS::EQ + 1];
+    hcoef<SS::TH>(ux, th, px);
+    hcoef<SS::TH>(uy, th, py);
+    double s = 0.0;
 #pragma unroll
     for (int k = 0; k <= SS::EQ; ++k) {
-        double b = 0.0, pm = 1.0;
+        double b = 0.0;
 #pragma unroll
-        for (int m = 0; m + k <= SS::EQ; ++m) {
-            b += pm * TB::hk.v[m][tq];
-            pm *= uy;
-        }
-        s += pk * TB::hk.v[k][tp] * b;
-        pk *= ux;
+        for (int m = 0; m + k <= SS::EQ; ++m) b += py[m] * TB::hk.v[m][tq];
+        s += px[k] * TB::hk.v[k][tp] * b;
     }
     return TB::rule.w[tp] * TB::rule.w[tq] * rho * s;
 }
@@ -1283,7 +1326,7 @@ __device__ double feq_one(double rho, double ux, double uy, int t) {
 // standing for it (the per-population form of emit_node)
 template <class ST, class SS>
 __device__ void emit_pop(const Buf &b, int copy, int i, int j, const Shift &sh, int t, double v, double rho,
-                         double ux, double uy, const Geo &g, const Phys &ph) {
+                         double ux, double uy, double th, const Geo &g, const Phys &ph) {
     typename ST::S *p0 = plane0<ST, SS>(b, copy) + (int64_t)t * b.plane;
     // absolute value x to entry (ii, jj), shifted by the reference of column ii
     auto put = [&](int ii, int jj, double x) {
@@ -1296,9 +1339,9 @@ __device__ void emit_pop(const Buf &b, int copy, int i, int j, const Shift &sh, 
     } else if (g.ybc == YBC_SHEAR) {
         if (j == 0) { put(i, -1, v); put(i, -2, v); }
         if (j == g.ny) {
-            const double neq = v - feq_one<SS>(rho, ux, uy, t);
-            put(i, g.ny + 1, feq_one<SS>(rho, ux + ph.shear, uy, t) + neq);
-            put(i, g.ny + 2, feq_one<SS>(rho, ux + 2.0 * ph.shear, uy, t) + neq);
+            const double neq = v - feq_one<SS>(rho, ux, uy, th, t);
+            put(i, g.ny + 1, feq_one<SS>(rho, ux + ph.shear, uy, th, t) + neq);
+            put(i, g.ny + 2, feq_one<SS>(rho, ux + 2.0 * ph.shear, uy, th, t) + neq);
         }
     } else {
         if (j < 2) put(i, j + g.nrow, v);
@@ -1308,7 +1351,8 @@ __device__ void emit_pop(const Buf &b, int copy, int i, int j, const Shift &sh, 
         if (i < 2) put(i + g.nx, j, v);
         if (i >= g.nx - 2) put(i - g.nx, j, v);
     } else if (i == 0 || i == g.nx - 1) {
-        const double gv = feq_one<SS>(i == 0 ? ph.rho_in : ph.rho_out, ux, uy, t) + (v - feq_one<SS>(rho, ux, uy, t));
+        const double gv =
+            feq_one<SS>(i == 0 ? ph.rho_in : ph.rho_out, ux, uy, th, t) + (v - feq_one<SS>(rho, ux, uy, th, t));
         if (i == 0) { put(-1, j, gv); put(-2, j, gv); }
         else { put(g.nx, j, gv); put(g.nx + 1, j, gv); }
     }
@@ -1321,19 +1365,19 @@ template <class ST, class LS, class HS>
 __device__ __forceinline__ void finish_pop(const StepArgs &A, const int cur, const int i, const int j, const int set,
                                            const int t) {
     const int copy = cur ^ 1;
-    double rho, ux, uy;
+    double rho, ux, uy, th;
     if (set == 0) {
         if (t >= LS::Q) return;
         double f[LS::Q];
         load_node_d<ST, LS>(A.self, copy, i, j, sh_of(A), f);
-        moments_d<LS>(f, rho, ux, uy);
-        emit_pop<ST, LS>(A.self, copy, i, j, sh_of(A), t, f[t], rho, ux, uy, A.g, A.ph);
+        moments_td<LS>(f, rho, ux, uy, th);
+        emit_pop<ST, LS>(A.self, copy, i, j, sh_of(A), t, f[t], rho, ux, uy, th, A.g, A.ph);
     } else {
         if (t >= HS::Q) return;
         double f[HS::Q];
         load_node_d<ST, HS>(A.other, copy, i, j, sh_of(A), f);
-        moments_d<HS>(f, rho, ux, uy);
-        emit_pop<ST, HS>(A.other, copy, i, j, sh_of(A), t, f[t], rho, ux, uy, A.g, A.ph);
+        moments_td<HS>(f, rho, ux, uy, th);
+        emit_pop<ST, HS>(A.other, copy, i, j, sh_of(A), t, f[t], rho, ux, uy, th, A.g, A.ph);
     }
 }
 
@@ -1370,21 +1414,21 @@ template <class ST, class LS, class HS>
 __device__ __forceinline__ void project_entry(const StepArgs &A, const int cur, const bool up, const int i,
                                               const int j, const int tq, const float *cl6) {
     const int copy = cur ^ 1;
-    double rho, ux, uy;
+    double rho, ux, uy, th;
     if (up) {
         double fs[LS::Q], out[HS::N];
         load_node_d<ST, LS>(A.self, copy, i, j, sh_of(A), fs);
-        project_col<LS, HS>(fs, tq, out, rho, ux, uy, cl6);
+        project_col<LS, HS>(fs, tq, out, rho, ux, uy, th, cl6);
 #pragma unroll
         for (int tp = 0; tp < HS::N; ++tp)
-            emit_pop<ST, HS>(A.other, copy, i, j, sh_of(A), tp + HS::N * tq, out[tp], rho, ux, uy, A.g, A.ph);
+            emit_pop<ST, HS>(A.other, copy, i, j, sh_of(A), tp + HS::N * tq, out[tp], rho, ux, uy, th, A.g, A.ph);
     } else {
         double fs[HS::Q], out[LS::N];
         load_node_d<ST, HS>(A.other, copy, i, j, sh_of(A), fs);
-        project_col<HS, LS>(fs, tq, out, rho, ux, uy);
+        project_col<HS, LS>(fs, tq, out, rho, ux, uy, th);
 #pragma unroll
         for (int tp = 0; tp < LS::N; ++tp)
-            emit_pop<ST, LS>(A.self, copy, i, j, sh_of(A), tp + LS::N * tq, out[tp], rho, ux, uy, A.g, A.ph);
+            emit_pop<ST, LS>(A.self, copy, i, j, sh_of(A), tp + LS::N * tq, out[tp], rho, ux, uy, th, A.g, A.ph);
     }
 }
 
@@ -1777,7 +1821,7 @@ __device__ __forceinline__ void closure_inputs(const ClosureNorm &cn, const doub
 // wave per CLOSURE_NB = 16 nodes.
 template <class ST, class LS, class HS>
 __global__ __launch_bounds__(64) void k_closure_infer(const StepArgs A) {
-    if constexpr (LS::N == 3 && HS::N == 6) {
+    if constexpr (LS::N == 3 && HS::N == 6 && !LS::TH) {
         __shared__ float xs[16][16];
         __shared__ float hs[16][MLP_NH + 4];
         __shared__ float rs[16];
@@ -1812,7 +1856,7 @@ __global__ __launch_bounds__(64) void k_closure_infer(const StepArgs A) {
 // bands; one wave per 16 nodes, row-major.  self = low set, other = high.
 template <class ST, class LS, class HS>
 __global__ __launch_bounds__(64) void k_closure_flags(const NodeArgs A) {
-    if constexpr (LS::N == 3 && HS::N == 6) {
+    if constexpr (LS::N == 3 && HS::N == 6 && !LS::TH) {
         __shared__ float xs[16][16];
         __shared__ float hs[16][MLP_NH + 4];
         __shared__ float rs[16];
@@ -1853,7 +1897,7 @@ __global__ __launch_bounds__(64) void k_closure_flags(const NodeArgs A) {
 // (indicator above theta).
 template <class ST, class HS, class LS>
 __global__ void k_closure_samples(const NodeArgs A) {
-    if constexpr (LS::N == 3 && HS::N == 6) {
+    if constexpr (LS::N == 3 && HS::N == 6 && !LS::TH) {
         const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         if (k >= A.nnodes) return;
         const int n = A.nodes[k];
@@ -1935,7 +1979,8 @@ __global__ void k_refresh(const NodeArgs A) {
     finish_node<ST, SS, OO>(A.self, A.other, A.cur, i, j, sh_of(A), f, false, proj, A.g, A.ph);
 }
 
-// f = f_eq(rho, u) on the nodes of this set (in0..2 = rho, ux, uy fields)
+// f = f_eq(rho, u, T) on the nodes of this set (in0..3 = rho, ux, uy, T
+// fields; T only on thermal sets, NULL = 1)
 template <class ST, class SS, class OO>
 __global__ void k_init_eq(const NodeArgs A) {
     int i, j;
@@ -1944,7 +1989,8 @@ __global__ void k_init_eq(const NodeArgs A) {
     if (!owns(r, A.self_high)) return;
     int n = j * A.g.nx + i;
     double f[SS::Q];
-    feq_d<SS>(A.in0[n], A.in1[n], A.in2[n], f);
+    const double th = (SS::TH && A.in3) ? A.in3[n] - 1.0 : 0.0;
+    feq_d<SS>(A.in0[n], A.in1[n], A.in2[n], th, f);
     store_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), f);
 }
 
@@ -1998,8 +2044,70 @@ __global__ void k_moments(const NodeArgs A) {
     A.out2[n] = uy;
 }
 
-// non-equilibrium indicator: max over (2,0), (1,1), (0,2) of
-// |a_km - rho ux^k uy^m| / rho
+// Thermal state of a node from its raw moments M1 = sum xi f,
+// M2_ij = sum xi_i xi_j f, M3_i = sum xi_i |xi|^2 f: rho, u, T = tr P / (2 rho)
+// with P_ij = M2_ij - rho u_i u_j, and the heat flux
+// q_i = 1/2 sum c_i |c|^2 f = (M3_i - 2 u_j M2_ij - u_i tr M2 + 2 rho u_i |u|^2) / 2
+// (c = xi - u expanded).
+struct ThermalState {
+    double rho, ux, uy, T, pxx, pxy, pyy, qx, qy;
+};
+template <class SS>
+__device__ ThermalState thermal_state(const double *f) {
+    using TB = typename SS::T;
+    constexpr int N = SS::N;
+    double m0 = 0, mx = 0, my = 0, mxx = 0, mxy = 0, myy = 0, m3x = 0, m3y = 0;
+#pragma unroll
+    for (int a = 0; a < SS::Q; ++a) {
+        const double x = TB::rule.x[a % N], y = TB::rule.x[a / N], x2 = x * x + y * y;
+        m0 += f[a];
+        mx += x * f[a];
+        my += y * f[a];
+        mxx += x * x * f[a];
+        mxy += x * y * f[a];
+        myy += y * y * f[a];
+        m3x += x * x2 * f[a];
+        m3y += y * x2 * f[a];
+    }
+    ThermalState t;
+    t.rho = m0;
+    t.ux = mx / m0;
+    t.uy = my / m0;
+    t.pxx = mxx - m0 * t.ux * t.ux;
+    t.pxy = mxy - m0 * t.ux * t.uy;
+    t.pyy = myy - m0 * t.uy * t.uy;
+    t.T = 0.5 * (t.pxx + t.pyy) / m0;
+    const double u2 = t.ux * t.ux + t.uy * t.uy, tr = mxx + myy;
+    t.qx = 0.5 * (m3x - 2.0 * (t.ux * mxx + t.uy * mxy) - t.ux * tr + 2.0 * m0 * t.ux * u2);
+    t.qy = 0.5 * (m3y - 2.0 * (t.ux * mxy + t.uy * myy) - t.uy * tr + 2.0 * m0 * t.uy * u2);
+    return t;
+}
+
+// Temperature and heat flux (qx, qy) of the nodes of this set (out0..2);
+// with A.mode = 1, the energy density 1/2 sum |xi|^2 f into out0 instead.
+template <class ST, class SS, class OO>
+__global__ void k_thermal(const NodeArgs A) {
+    int i, j;
+    if (!node_index(A.g, i, j)) return;
+    int r = region_at(i, j, A.g);
+    if (!(owns(r, A.self_high) || (!A.self_high && r == REG_IFACE))) return;
+    double f[SS::Q];
+    load_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), f);
+    const ThermalState t = thermal_state<SS>(f);
+    const int n = j * A.g.nx + i;
+    if (A.mode == 1) {
+        A.out0[n] = 0.5 * (t.pxx + t.pyy) + 0.5 * t.rho * (t.ux * t.ux + t.uy * t.uy);
+        return;
+    }
+    A.out0[n] = t.T;
+    A.out1[n] = t.qx;
+    A.out2[n] = t.qy;
+}
+
+// non-equilibrium indicator, the 'B' parameter of Sec. 2.2 made
+// dimensionless.  Isothermal sets: max over (2,0), (1,1), (0,2) of
+// |a_km - rho ux^k uy^m| / rho.  Thermal sets: max of |P_ij - p delta_ij| / p
+// (ij = xx, xy, yy) and |q_i| / (p sqrt(T)), p = rho T.
 template <class ST, class SS, class OO>
 __global__ void k_indicator(const NodeArgs A) {
     int i, j;
@@ -2010,6 +2118,17 @@ __global__ void k_indicator(const NodeArgs A) {
     constexpr int N = SS::N;
     double f[SS::Q];
     load_node_d<ST, SS>(A.self, A.cur, i, j, sh_of(A), f);
+    if constexpr (SS::TH) {
+        const ThermalState t = thermal_state<SS>(f);
+        const double p = t.rho * t.T, pq = p * sqrt(t.T);
+        double b = fabs(t.pxx - p) / p;
+        b = fmax(b, fabs(t.pxy) / p);
+        b = fmax(b, fabs(t.pyy - p) / p);
+        b = fmax(b, fabs(t.qx) / pq);
+        b = fmax(b, fabs(t.qy) / pq);
+        A.out0[j * A.g.nx + i] = b;
+        return;
+    }
     double a00 = 0, a10 = 0, a01 = 0, a20 = 0, a11 = 0, a02 = 0;
 #pragma unroll
     for (int a = 0; a < SS::Q; ++a) {
@@ -2046,7 +2165,7 @@ __global__ void k_convert(const NodeArgs A) {
         const double *cl = nullptr;
         if (A.closure && A.self_high) cl = A.closure + (int64_t)(j * A.g.nx + i) * SS::Q;
         double cl36[SS::Q];
-        if constexpr (OO::N == 3 && SS::N == 6) {
+        if constexpr (OO::N == 3 && SS::N == 6 && !SS::TH) {
             // D2Q9 -> D2Q36 with the learned closure: the network's six
             // coefficients, zero elsewhere
             if (A.clw && A.self_high) {
@@ -2069,10 +2188,10 @@ __global__ void k_convert(const NodeArgs A) {
 }
 
 // Interface rows of the interpolation/extrapolation mode (Sec. 2.2): one
-// thread per column and interface.  rho_I, u_I = averages of the low-side
-// neighbour l and high-side neighbour h; in each set the population is the
-// equilibrium at (rho_I, u_I) plus the same-side neighbour's
-// non-equilibrium part.  The row beyond I on each side gets a copy of I in
+// thread per column and interface.  rho_I, u_I (and on thermal sets T_I) =
+// averages of the low-side neighbour l and high-side neighbour h; in each
+// set the population is the equilibrium at (rho_I, u_I, T_I) plus the
+// same-side neighbour's non-equilibrium part.  The row beyond I on each side gets a copy of I in
 // the other side's set (the second stencil row).  `recompute` = 0 keeps
 // the stored I rows and only rebuilds copies and images.
 template <class ST, class LS, class HS>
@@ -2100,16 +2219,18 @@ __global__ void k_paper_iface(const NodeArgs A, int copy, int recompute) {
         double fl[LS::Q], fh[HS::Q], e1[HS::Q > LS::Q ? HS::Q : LS::Q], e2[HS::Q > LS::Q ? HS::Q : LS::Q];
         load_node_d<ST, LS>(BL, copy, i, jl, sh_of(A), fl);
         load_node_d<ST, HS>(BH, copy, i, jh, sh_of(A), fh);
-        double rl, uxl, uyl, rh, uxh, uyh;
-        moments_d<LS>(fl, rl, uxl, uyl);
-        moments_d<HS>(fh, rh, uxh, uyh);
+        double rl, uxl, uyl, thl, rh, uxh, uyh, thh;
+        moments_td<LS>(fl, rl, uxl, uyl, thl);
+        moments_td<HS>(fh, rh, uxh, uyh, thh);
         double rI = 0.5 * (rl + rh), uxI = 0.5 * (uxl + uxh), uyI = 0.5 * (uyl + uyh);
-        feq_d<LS>(rI, uxI, uyI, e1);
-        feq_d<LS>(rl, uxl, uyl, e2);
+        // T_I - 1 = ((T_l - 1) + (T_h - 1)) / 2
+        double thI = 0.5 * (thl + thh);
+        feq_d<LS>(rI, uxI, uyI, thI, e1);
+        feq_d<LS>(rl, uxl, uyl, thl, e2);
 #pragma unroll
         for (int a = 0; a < LS::Q; ++a) fL[a] = e1[a] + (fl[a] - e2[a]);
-        feq_d<HS>(rI, uxI, uyI, e1);
-        feq_d<HS>(rh, uxh, uyh, e2);
+        feq_d<HS>(rI, uxI, uyI, thI, e1);
+        feq_d<HS>(rh, uxh, uyh, thh, e2);
 #pragma unroll
         for (int a = 0; a < HS::Q; ++a) fH[a] = e1[a] + (fh[a] - e2[a]);
     } else {

@@ -25,12 +25,14 @@ using PairFn = void (*)(const lbi::StepArgs &low, const lbi::StepArgs &high, int
 
 struct KernelSet {
     int storage, nS, eqS, nO, eqO;
+    int th;                 // thermal sets (temperature from each node's energy moment)
     StepFn update;
     TimedFn update_timed;   // the same launch bracketed by kernel start/stop events
     StepFn finish;        // valid when `self` is the low set of the pair
     StepFn project_halo;  // likewise
     ProjFinFn project_finish;   // likewise
     NodeFn refresh, init_eq, set_pop, get_pop, moments, indicator, convert;
+    NodeFn thermal;         // temperature and heat flux (or energy density) per node
     IfaceFn paper_iface;   // valid when `self` is the low set of the pair
     ProjFn project;        // FP64 projection self -> partner
     StepFn closure_infer;   // learned-closure inference of the lifted nodes (self = low set)
@@ -73,5 +75,8 @@ void launch_to_bf16(const float *p, uint16_t *out, hipStream_t s);
 Registry registry_f64();
 Registry registry_f32();
 Registry registry_bf16();
+// thermal set pairs (FP64 and FP32 storage)
+Registry registry_f64_thermal();
+Registry registry_f32_thermal();
 
 }  // namespace lbk

@@ -101,11 +101,14 @@ struct Tab {
 };
 
 // A velocity set with its equilibrium order (the force uses the same order).
-template <int N_, int EQ_>
+// TH: thermal lattice -- every node's temperature comes from its energy
+// moment and enters the equilibrium's Hermite coefficients; otherwise T = 1.
+template <int N_, int EQ_, bool TH_ = false>
 struct VSet {
     static constexpr int N = N_;
     static constexpr int Q = N_ * N_;
     static constexpr int EQ = EQ_;
+    static constexpr bool TH = TH_;
     using T = Tab<N_>;
 };
 
@@ -114,6 +117,7 @@ struct NoSet {
     static constexpr int N = 0;
     static constexpr int Q = 0;
     static constexpr int EQ = 0;
+    static constexpr bool TH = false;
 };
 
 }  // namespace lbt

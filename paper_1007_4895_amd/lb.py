@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("gx", C.c_double), ("gy", C.c_double), ("u_wall", C.c_double * 4),
         ("rho_in", C.c_double), ("rho_out", C.c_double),
         ("u_osc", C.c_double), ("omega_osc", C.c_double), ("shear_top", C.c_double),
+        ("T_wall", C.c_double * 2), ("thermal", C.c_int32), ("reserved_", C.c_int32),
     ]
 
 
@@ -69,6 +70,9 @@ def lib():
             "lb_set_regions": (C.c_int, [_vp, _ip, _ip]),
             "lb_get_regions": (C.c_int, [_vp, _ip, _ip]),
             "lb_init_equilibrium": (C.c_int, [_vp, _dp, _dp, _dp]),
+            "lb_init_equilibrium_thermal": (C.c_int, [_vp, _dp, _dp, _dp, _dp]),
+            "lb_thermal_moments": (C.c_int, [_vp, _dp, _dp, _dp, C.c_int32]),
+            "lb_energy": (C.c_int, [_vp, _dp]),
             "lb_step": (C.c_int, [_vp, C.c_int64]),
             "lb_moments": (C.c_int, [_vp, _dp, _dp, _dp, C.c_int32]),
             "lb_conservation": (C.c_int, [_vp, _dp]),
@@ -137,7 +141,7 @@ def make_params(nx, ny, *, kn, n_low=3, n_high=3, eq_low=2, eq_high=None, storag
                 iface=IFACE_HERMITE, tau_mode=TAU_CONST, xbc=XBC_PERIODIC, ybc=YBC_WALLS,
                 tile_w=0, rho_ref=1.0, cfl=0.5, dt=0.0, gx=0.0, gy=0.0,
                 u_wall=((0.0, 0.0), (0.0, 0.0)), rho_in=1.0, rho_out=1.0, u_osc=0.0,
-                omega_osc=0.0, shear_top=0.0) -> Params:
+                omega_osc=0.0, shear_top=0.0, thermal=False, T_wall=(1.0, 1.0)) -> Params:
     p = Params()
     _check(lib().lb_params_default(C.byref(p)))
     p.nx, p.ny = nx, ny
@@ -154,6 +158,8 @@ def make_params(nx, ny, *, kn, n_low=3, n_high=3, eq_low=2, eq_high=None, storag
     p.rho_in, p.rho_out = rho_in, rho_out
     p.u_osc, p.omega_osc = u_osc, omega_osc
     p.shear_top = shear_top
+    p.thermal = 1 if thermal else 0
+    p.T_wall[0], p.T_wall[1] = T_wall
     return p
 
 
@@ -254,10 +260,14 @@ class Lattice:
         return tuple(r)
 
     # ----------------------------------------------------------------- state
-    def init_equilibrium(self, rho=None, ux=None, uy=None):
-        arrs = [None if a is None else _f64(np.broadcast_to(a, (self.nrow, self.nx))) for a in (rho, ux, uy)]
+    def init_equilibrium(self, rho=None, ux=None, uy=None, T=None):
+        """Equilibrium start; T (thermal lattices only) defaults to 1."""
+        arrs = [None if a is None else _f64(np.broadcast_to(a, (self.nrow, self.nx))) for a in (rho, ux, uy, T)]
         ptrs = [None if a is None else _d(a) for a in arrs]
-        _check(lib().lb_init_equilibrium(self._h, *ptrs))
+        if T is None:
+            _check(lib().lb_init_equilibrium(self._h, *ptrs[:3]))
+        else:
+            _check(lib().lb_init_equilibrium_thermal(self._h, *ptrs))
 
     def step(self, n=1):
         _check(lib().lb_step(self._h, int(n)))
@@ -281,6 +291,19 @@ class Lattice:
         out = np.zeros(3)
         _check(lib().lb_conservation(self._h, _d(out)))
         return out
+
+    def thermal_moments(self):
+        """Temperature and heat flux (qx, qy) of every node, [ny+1][nx]."""
+        shp = (self.nrow, self.nx)
+        T, qx, qy = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+        _check(lib().lb_thermal_moments(self._h, _d(T), _d(qx), _d(qy), 0))
+        return T, qx, qy
+
+    def energy(self):
+        """Total energy: sum over nodes of 1/2 sum |xi|^2 f."""
+        out = np.zeros(1)
+        _check(lib().lb_energy(self._h, _d(out)))
+        return float(out[0])
 
     def get_populations(self, which):
         f = np.zeros((self.Q[which], self.nrow, self.nx))
