@@ -123,6 +123,103 @@ def large_section(lb, W, torch, steps):
     return out
 
 
+def thermal_lattice(lb, W, *, n_low, eq_low, bands, nx=None, ny=None, kn=None, storage=None, u_wall=None,
+                    T_wall=None, dt=0.0):
+    c = W.THERMAL_COUETTE
+    p = lb.make_params(nx or c["nx"], ny or c["ny"], kn=kn or c["kn"], n_low=n_low, eq_low=eq_low,
+                       n_high=c["n_high"], eq_high=c["eq_high"], u_wall=u_wall or c["u_wall"],
+                       storage=storage or c["storage"], thermal=True, T_wall=T_wall or c["T_wall"], dt=dt)
+    L = lb.Lattice(p)
+    L.set_regions(*bands)
+    L.init_equilibrium()
+    return L
+
+
+def thermal_section(lb, W, torch, steps, shape, iso_kernel_ms=None, quick=False):
+    """Thermal Couette channel at the C2 size: coupled (the isothermal
+    run's work shape; the autotuner times per-set launches, which thermal
+    D2Q9 sets do not use) and all-D2Q36 (uniform set, autotuned) throughput,
+    the merged update's roofline from kernel events, and what it costs over
+    the isothermal update; then the physics check on a small x-uniform
+    channel: temperature and velocity profiles of M-D2Q9-36 and M-D2Q16-36
+    against all-D2Q36."""
+    import numpy as np
+
+    c = W.THERMAL_COUETTE
+    nodes = c["nx"] * (c["ny"] + 1)
+    out = {"workload": f"thermal_couette: {c['nx']}x{c['ny'] + 1}, walls -/+{c['u_wall'][1][0]} at T "
+                       f"{c['T_wall'][0]}/{c['T_wall'][1]}, Kn={c['kn']}, thermal D2Q36 (order 4) in 64 rows at "
+                       "each wall, thermal D2Q9 core, FP32", "nodes": nodes}
+    L = thermal_lattice(lb, W, n_low=c["n_low"], eq_low=c["eq_low"], bands=c["bands"])
+    L.set_work_shape(*shape)
+    cnt = L.region_counts()
+    L.step(200)
+    sec = timed(L, steps, torch)
+    L.set_timing(True)
+    L.step(2000)
+    ms_h, n_h, _, _ = L.kernel_times()
+    L.set_timing(False)
+    avg = ms_h / max(n_h, 1)
+    alg = 4 * 2 * (9 * cnt[0] + 36 * cnt[1])
+    T, _, qy = L.thermal_moments()
+    out["coupled"] = {"mlups": round(nodes * steps / sec / 1e6, 1), "us_per_step": round(1e6 * sec / steps, 2),
+                      "update_kernel_us": round(1e3 * avg, 2),
+                      "update_kernel_gbs": round(alg / (avg * 1e-3) / 1e9, 1),
+                      "update_kernel_frac": round(alg / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "work_shape": ",".join(str(v) for v in shape[0] + shape[1]),
+                      "T_range": [round(float(T.min()), 5), round(float(T.max()), 5)],
+                      "finite": bool(np.all(np.isfinite(T)))}
+    if iso_kernel_ms:
+        out["coupled"]["kernel_time_vs_isothermal"] = round(avg / iso_kernel_ms, 3)
+    del L
+    if quick:
+        return out
+    La = thermal_lattice(lb, W, n_low=c["n_high"], eq_low=c["eq_high"], bands=(0, 0))
+    La.autotune(100)
+    La.step(200)
+    sec_a = timed(La, steps, torch)
+    out["all_d2q36"] = {"mlups": round(nodes * steps / sec_a / 1e6, 1), "us_per_step": round(1e6 * sec_a / steps, 2)}
+    out["speedup_vs_all_d2q36"] = round(sec_a / sec, 3)
+    out["timed_steps"] = steps
+    del La
+    print(f"thermal: {out}", flush=True)
+
+    # physics: x-uniform channel, steady state, FP64
+    ph = c["physics"]
+    x6, _ = np.polynomial.hermite_e.hermegauss(6)
+    dt = 0.5 / float(np.max(x6))
+    phys = {"geometry": f"{ph['nx']}x{ph['ny'] + 1}, Kn={ph['kn']}, {ph['bands']}-row bands, {ph['steps']} steps, "
+                        "FP64", "cases": {}}
+    for case, cw in ph["cases"].items():
+        prof = {}
+        cfgs = [("all_d2q36", 6, 4, (0, 0))] + [(f"m_d2q{nl * nl}_36", nl, el, (ph["bands"], ph["bands"]))
+                                                  for nl, el, _, _ in ph["pairs"]]
+        for name, nl, el, bands in cfgs:
+            L = thermal_lattice(lb, W, n_low=nl, eq_low=el, bands=bands, nx=ph["nx"], ny=ph["ny"], kn=ph["kn"],
+                                storage=ph["storage"], u_wall=cw["u_wall"], T_wall=cw["T_wall"], dt=dt)
+            L.step(ph["steps"])
+            T, _, qy = L.thermal_moments()
+            _, ux, _ = L.moments()
+            prof[name] = (T[:, 0], ux[:, 0], qy[:, 0])
+            del L
+        Ta, ua, qa = prof["all_d2q36"]
+        row = {"T_mid_all_d2q36": round(float(Ta[ph["ny"] // 2]), 6)}
+        for name in prof:
+            if name == "all_d2q36":
+                continue
+            Tc, uc, qc = prof[name]
+            r = {"e_T": float(np.linalg.norm(Tc - Ta) / np.linalg.norm(Ta - 1.0))}
+            if cw["u_wall"][1][0] != 0.0:
+                r["e_u"] = float(np.linalg.norm(uc - ua) / np.linalg.norm(ua))
+            if case == "conduction":
+                j = ph["ny"] // 2
+                r["q_mid_over_all_d2q36"] = round(float(qc[j] / qa[j]), 4)
+            row[name] = r
+        phys["cases"][case] = row
+    out["physics"] = phys
+    return out
+
+
 def c3_lattice(lb, W, storage, all_high, bmin):
     """The pressure-driven channel (D2Q9 / D2Q36 order 4) from a linear
     density ramp at rest, bands of bmin rows to start with."""
@@ -376,6 +473,10 @@ def main():
     ap.add_argument("--closure-only", action="store_true", help="run only the learned-closure section")
     ap.add_argument("--c3-only", action="store_true", help="run only the pressure-channel section (profiling)")
     ap.add_argument("--large-only", action="store_true", help="run only the 4096-column section (profiling)")
+    ap.add_argument("--no-thermal", action="store_true", help="skip the thermal Couette section")
+    ap.add_argument("--thermal-only", action="store_true",
+                    help="run only the thermal Couette section (with --quick: its coupled run only, for "
+                         "profiling; work shape from --shape, default 1,2,1,1)")
     ap.add_argument("--profile-steps", type=int, default=2000,
                     help="steps of the kernel-timing pass (the dominant kernel's roofline)")
     ap.add_argument("--shape", type=str, default="",
@@ -408,6 +509,10 @@ def main():
         return
     if args.large_only:
         print(json.dumps({"c2_wide_4096": large_section(lb, W, torch, 2000)}))
+        return
+    if args.thermal_only:
+        v = [int(x) for x in (args.shape or "1,2,1,1").split(",")]
+        print(json.dumps({"thermal_couette": thermal_section(lb, W, torch, 5000, (v[:2], v[2:]), quick=args.quick)}))
         return
 
     if args.copy_calib:
@@ -552,6 +657,10 @@ def main():
     if not args.no_large:
         out["c2_wide_4096"] = large_section(lb, W, torch, 2000)
         print(f"wide: {out['c2_wide_4096']}", flush=True)
+
+    # ------------- thermal Couette channel (temperature in every kernel)
+    if not args.no_thermal:
+        out["thermal_couette"] = thermal_section(lb, W, torch, 5000, (list(strips), list(orders)), avg_ms)
 
     # ------------------- pressure channel with its periodic re-decomposition
     if not args.no_c3:

@@ -29,6 +29,14 @@ Workloads (all synthetic: the paper's cases are analytic channel flows):
                Kn = 0.005 of the 400-node height), D2Q36 within 10 lambda
                of the plate (20 rows), D2Q9 beyond; started from the
                far-field shear flow, FP64.
+  thermal_couette  thermal Couette channel, the C2 geometry (nx = 1024 x
+               ny = 512): walls moving -/+0.05 at temperatures 1.05 / 0.95,
+               Kn = 0.01, thermal D2Q36 (4th order) in 64 rows at each wall,
+               thermal D2Q9 core, FP32, started at rest at T = 1.  Physics
+               check on an x-uniform channel nx = 4 x ny = 128, Kn = 0.05,
+               16-row bands: steady conduction (walls at rest, T 1.02 /
+               0.98) and shear heating (walls -/+0.1 at T = 1), M-D2Q9-36
+               and M-D2Q16-36 against all-D2Q36, FP64.
   batch_c5     128 independent channels, nx = 8 (periodic), ny uniform in
                [32, 512], Kn log-spaced in [0.01, 1], near-wall bands of
                8-64 rows (at most a third of the channel), velocity-set
@@ -91,6 +99,14 @@ OSC_COUETTE = dict(nx=8, ny=100, kn=0.0178, kn_sweep=(0.0178, 0.1, 0.3), u_osc=0
                    bands=(15, 15), pairs=((3, 2, 6, 4), (4, 3, 6, 4)), storage="f64", periods=3)
 
 KRAMERS = dict(nx=8, ny=400, kn=0.005, shear=1e-4, band=20, storage="f64")
+
+THERMAL_COUETTE = dict(nx=1024, ny=512, kn=0.01, n_low=D2Q9, n_high=D2Q36, eq_low=2, eq_high=4,
+                       u_wall=((-0.05, 0.0), (0.05, 0.0)), T_wall=(1.05, 0.95), bands=(64, 64), storage="f32",
+                       physics=dict(nx=4, ny=128, kn=0.05, bands=16, steps=80000, storage="f64",
+                                    pairs=((3, 2, 6, 4), (4, 3, 6, 4)),
+                                    cases={"conduction": dict(u_wall=((0.0, 0.0), (0.0, 0.0)), T_wall=(1.02, 0.98)),
+                                           "shear_heating": dict(u_wall=((-0.1, 0.0), (0.1, 0.0)),
+                                                                 T_wall=(1.0, 1.0))}))
 
 BATCH_C5 = dict(count=128, nx=8, ny_range=(32, 512), kn_range=(0.01, 1.0), band_range=(8, 64),
                 pairs=((3, 2, 4, 3), (3, 2, 6, 4), (4, 3, 6, 4)), u_wall=0.05, gx=1e-6, storage="f32",

@@ -297,3 +297,33 @@ def test_thermal_d2q9_without_high_nodes(oracle, lb, storage):
         num = np.sqrt(np.sum((uxg - uxo) ** 2 + (uyg - uyo) ** 2))
         assert num / np.sqrt(np.sum(uxo ** 2 + uyo ** 2)) < 1e-5
         assert np.max(np.abs(T_g - T_o)) < 1e-6
+
+
+def test_thermal_couette_full_size_x_uniform(oracle, lb):
+    """The benchmark's thermal workload at full size (1024 x 513, FP32, in
+    the merged launch of the benchmark's work shape): the flow stays
+    bit-for-bit x-uniform, so every column is checked against the oracle
+    run at nx = 4."""
+    c = W.THERMAL_COUETTE
+    steps = 1000
+    x, _ = oracle.gh_rule(6)
+    dt = 0.5 / float(np.max(x))
+    kw = dict(n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"], eq_high=c["eq_high"], kn=c["kn"],
+              u_wall=c["u_wall"], T_wall=c["T_wall"])
+    G = lb.Lattice(lb.make_params(c["nx"], c["ny"], storage=c["storage"], dt=dt, thermal=True, **kw))
+    G.set_regions(*c["bands"])
+    G.set_work_shape((1, 2), (1, 1))
+    G.init_equilibrium()
+    G.step(steps)
+    r_g, uxg, uyg = G.moments()
+    T_g, _, qyg = G.thermal_moments()
+    assert np.all(uxg == uxg[:, :1]) and np.all(T_g == T_g[:, :1]) and np.all(r_g == r_g[:, :1])
+    O = oracle.Lattice(4, c["ny"], dt=dt, thermal=True, **kw)
+    O.set_regions(*c["bands"])
+    O.init_equilibrium()
+    O.step(steps)
+    _, uxo, _ = O.moments()
+    T_o, _, qyo = O.thermal_moments()
+    assert np.linalg.norm(uxg[:, 0] - uxo[:, 0]) / np.linalg.norm(uxo[:, 0]) < 1e-5
+    assert np.max(np.abs(T_g[:, 0] - T_o[:, 0])) < 1e-6
+    assert np.max(np.abs(T_o[:, 0] - 1.0)) > 1e-2     # the walls have heated / cooled the gas
