@@ -2,16 +2,20 @@
 """Benchmark: coupled D2Q9/D2Q36 lattice Boltzmann channel on one MI355X.
 
 Workload (synthetic, the paper's cases are analytic channel flows): body-force
-Poiseuille channel 1024 x 513 nodes, g = 1e-6, Kn = 0.05, D2Q36 with a
-4th-order equilibrium in 64 rows at each wall, D2Q9 (2nd order) elsewhere,
-Hermite-moment interface, FP32 weight-shifted populations.  One step = one
-full time step of the hot path (the update of both sets in one launch, with
-walls and periodic images, then the interface projections).
+Poiseuille channel 1024 x 513 nodes, g = 1e-6, D2Q36 with a 4th-order
+equilibrium in 64 rows at each wall, D2Q9 (2nd order) elsewhere,
+Hermite-moment interface, FP32 weight-shifted populations, timed at Kn = 0.01
+(the swept Kn whose 64-row bands meet the 1e-3 velocity-error gate; a step
+costs the same at any Kn).  One step = one full time step of the hot path
+(the update of both sets in one launch, with walls and periodic images, then
+the interface projections).
 
 Prints one JSON line: coupled MLUPS (value), the all-D2Q36 MLUPS of the same
 case, algorithmic HBM GB/s, the roofline of the dominant kernel (the merged
 update of both sets), the model error of the coupled run against all-D2Q36
-per Kn, the 128-channel batch against one launch per case, and the FP64 CPU
+per Kn (0.01, 0.05, 0.1) and band width, the wider channel, the thermal
+Couette channel, the pressure channel with its re-decompositions, the learned
+closure, the 128-channel batch against one launch per case, and the FP64 CPU
 oracle timed on a bounded sample.
 """
 from __future__ import annotations

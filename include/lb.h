@@ -24,9 +24,14 @@
  *    Population alpha = p + n*q has velocity (x_p, x_q), abscissae ascending.
  *  - Host arrays of lattice fields are [ny+1][nx] doubles, row j slow.
  *    Population arrays are [Q][ny+1][nx] doubles.
- *  - Memory: the caller owns one device workspace (size from
- *    lb_workspace_bytes) and a HIP stream; the library never allocates device
- *    memory.  Host pointers are only read or written during the call.
+ *  - Memory: the caller owns one device workspace per lattice (size from
+ *    lb_workspace_bytes) and a HIP stream; lattice calls allocate no device
+ *    memory.  Device allocations happen only in lb_batch_create (the batch's
+ *    descriptor table and work lists, freed by lb_batch_destroy), in
+ *    lb_mlp_forward / lb_mlp_loss_grad callers' workspaces (caller-owned) and
+ *    in the lb_closure_eval test hook (a temporary weight copy); the
+ *    allocation-free lb_mlp_forward_noalloc uses a library-owned device array.
+ *    Host pointers are only read or written during the call.
  *  - Asynchrony: lb_step and the on-device variants enqueue work on the
  *    stream and return; errors found by kernels surface at the next call that
  *    synchronises (lb_conservation, host-side moments, get_* calls).
@@ -153,13 +158,16 @@ lb_status lb_init_equilibrium_thermal(lb_lattice *L, const double *rho, const do
  * step (time-dependent kernel arguments, no device-side state). */
 lb_status lb_step(lb_lattice *L, int64_t nsteps);
 
-/* Density and velocity of every node ([ny+1][nx], FP64; interface rows report
- * the interpolated values).  on_device != 0: the three pointers are device
- * memory and the call is asynchronous; else host memory and the call waits. */
+/* Density and velocity of every node ([ny+1][nx], FP64): the zeroth and first
+ * Hermite coefficients of Eq. (an), rho = sum f, rho u = sum xi f, in the
+ * node's own set (interface rows report the interpolated values).
+ * on_device != 0: the three pointers are device memory and the call is
+ * asynchronous; else host memory and the call waits. */
 lb_status lb_moments(lb_lattice *L, double *rho, double *ux, double *uy, int32_t on_device);
 
-/* out[0..2] = sum rho, sum rho ux, sum rho uy over all nodes, reduced in FP64
- * in a fixed order (deterministic).  Waits.  LB_EUNSTABLE if not finite. */
+/* out[0..2] = sum rho, sum rho ux, sum rho uy over all nodes (the moments
+ * of lb_moments, Eq. (an)), reduced in FP64 in a fixed order
+ * (deterministic).  Waits.  LB_EUNSTABLE if not finite. */
 lb_status lb_conservation(lb_lattice *L, double out[3]);
 
 /* Temperature T = (sum xi^2 f / rho - u^2) / 2 and heat flux
@@ -226,7 +234,10 @@ lb_status lb_kernel_times(lb_lattice *L, double *ms_high, int64_t *n_high, doubl
  * set is D2Q9 and both sets have nodes): the high set's work items and the
  * D2Q9 items share the launch instead of running back to back.  Results
  * are identical either way.  In timing mode the merged launch is the
- * dominant kernel reported by lb_kernel_times. */
+ * dominant kernel reported by lb_kernel_times.  Thermal lattices with a
+ * D2Q9 low set always use the merged launch (also when the high set has no
+ * nodes): disabling it returns LB_EUNSUPPORTED, as do lb_set_concurrency(1)
+ * and lb_autotune on them (both need the D2Q9 update launched alone). */
 lb_status lb_set_merged_update(lb_lattice *L, int32_t enable);
 
 /* Run the low set's update and its projection into the high set on a
@@ -356,10 +367,10 @@ lb_status lb_set_closure_flags(lb_lattice *L, int32_t enable);
  * lattice is the same computation as lb_step (bit-identical results).
  *
  * The lattices stay owned by the caller and must outlive the batch; they
- * must share a storage type, use the Hermite interface, have no learned
- * closure set and no oscillating wall (graph replays repeat the captured
- * kernel arguments), and be at the same copy parity (same step count
- * modulo 2).
+ * must share a storage type, be isothermal, use the Hermite interface, have
+ * no learned closure set and no oscillating wall (graph replays repeat the
+ * captured kernel arguments), and be at the same copy parity (same step
+ * count modulo 2).
  * A lattice stepped on its own in between makes lb_batch_step fail with
  * LB_ESTATE; region changes are picked up (the work lists are rebuilt).
  * The batch allocates its descriptor table and work lists with hipMalloc.
