@@ -592,7 +592,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"poiseuille_c2: 1024x513 body-force channel, g=1e-6, Kn={kn_t}, D2Q36 (order 4) "
                                "in 64 rows at each wall, D2Q9 core, Hermite interface, FP32 weight-shifted "
-                               "populations", "nodes": nodes, "d2q36_nodes": counts[1], "d2q9_nodes": counts[0]},
+                               "populations", "nodes": nodes, "d2q36_nodes": counts[1], "d2q9_nodes": counts[0],
+                   "courant": 0.5,
+                   "courant_note": "per axis, fastest abscissa; stable because the channel stays bitwise x-uniform"},
         "hbm_gbs_algorithmic": round(alg_bytes_step * args.steps / sec / 1e9, 1),
         "strip_rows": {"d2q9": strips[0], "d2q36": strips[1]},
         "work_shape": ",".join(str(v) for v in (*strips, *orders)),
