@@ -66,7 +66,7 @@ def host_cpu() -> str:
 def make(lb, W, kn, all_high, bands=None):
     c = W.POISEUILLE_C2
     p = lb.make_params(c["nx"], c["ny"], kn=kn, n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"],
-                       eq_high=c["eq_high"], gx=c["gx"], storage=c["storage"])
+                       eq_high=c["eq_high"], gx=c["gx"], storage=c["storage"], cfl=c["cfl"])
     L = lb.Lattice(p)
     if all_high:
         L.set_regions(c["ny"] + 1, 0)
@@ -95,14 +95,14 @@ def large_section(lb, W, torch, steps):
 
     def mk(all_high):
         p = lb.make_params(nx, c["ny"], kn=KN_TIMED, n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"],
-                           eq_high=c["eq_high"], gx=c["gx"], storage=c["storage"])
+                           eq_high=c["eq_high"], gx=c["gx"], storage=c["storage"], cfl=c["cfl"])
         L = lb.Lattice(p)
         L.set_regions(*((c["ny"] + 1, 0) if all_high else c["bands"]))
         L.init_equilibrium()
         return L
 
     out = {"workload": f"poiseuille_c2 widened: {nx}x{c['ny'] + 1}, Kn={KN_TIMED}, D2Q36 (order 4) in 64 rows at "
-                       "each wall, D2Q9 core, FP32", "nodes": nodes}
+                       f"each wall, D2Q9 core, FP32, Courant {c['cfl']}", "nodes": nodes}
     for name, all_high in (("coupled", False), ("all_d2q36", True)):
         L = mk(all_high)
         cnt = L.region_counts()
@@ -132,7 +132,8 @@ def thermal_lattice(lb, W, *, n_low, eq_low, bands, nx=None, ny=None, kn=None, s
     c = W.THERMAL_COUETTE
     p = lb.make_params(nx or c["nx"], ny or c["ny"], kn=kn or c["kn"], n_low=n_low, eq_low=eq_low,
                        n_high=c["n_high"], eq_high=c["eq_high"], u_wall=u_wall or c["u_wall"],
-                       storage=storage or c["storage"], thermal=True, T_wall=T_wall or c["T_wall"], dt=dt)
+                       storage=storage or c["storage"], thermal=True, T_wall=T_wall or c["T_wall"], cfl=c["cfl"],
+                       dt=dt)
     L = lb.Lattice(p)
     L.set_regions(*bands)
     L.init_equilibrium()
@@ -153,7 +154,7 @@ def thermal_section(lb, W, torch, steps, shape, iso_kernel_ms=None, quick=False)
     nodes = c["nx"] * (c["ny"] + 1)
     out = {"workload": f"thermal_couette: {c['nx']}x{c['ny'] + 1}, walls -/+{c['u_wall'][1][0]} at T "
                        f"{c['T_wall'][0]}/{c['T_wall'][1]}, Kn={c['kn']}, thermal D2Q36 (order 4) in 64 rows at "
-                       "each wall, thermal D2Q9 core, FP32", "nodes": nodes}
+                       f"each wall, thermal D2Q9 core, FP32, Courant {c['cfl']}", "nodes": nodes}
     L = thermal_lattice(lb, W, n_low=c["n_low"], eq_low=c["eq_low"], bands=c["bands"])
     L.set_work_shape(*shape)
     cnt = L.region_counts()
@@ -398,7 +399,7 @@ def batch_section(lb, W, torch):
     lats = []
     for c in W.batch_cases():
         p = lb.make_params(c["nx"], c["ny"], kn=c["kn"], n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"],
-                           eq_high=c["eq_high"], storage=c["storage"], u_wall=c["u_wall"], gx=c["gx"])
+                           eq_high=c["eq_high"], storage=c["storage"], u_wall=c["u_wall"], gx=c["gx"], cfl=c["cfl"])
         L = lb.Lattice(p)
         L.set_regions(*c["bands"])
         L.init_equilibrium()
@@ -448,7 +449,8 @@ def batch_section(lb, W, torch):
     mlups_pc = nodes * n_pc / sec_pc / 1e6
     gbs = alg * n_b / sec_b / 1e9
     return {"workload": "128 channels nx=8 (periodic), ny uniform in [32,512], Kn log-spaced in [0.01,1], "
-                        "bands 8-64 rows, D2Q9/D2Q16, D2Q9/D2Q36, D2Q16/D2Q36, Couette/Poiseuille, FP32",
+                        "bands 8-64 rows, D2Q9/D2Q16, D2Q9/D2Q36, D2Q16/D2Q36, Couette/Poiseuille, FP32, "
+                        f"Courant {c5['cfl']}",
             "nodes": nodes, "mlups_batch": round(mlups_b, 1), "mlups_one_launch_per_case": round(mlups_pc, 1),
             "speedup": round(mlups_b / mlups_pc, 2), "us_per_step_batch": round(1e6 * sec_b / n_b, 2),
             "hbm_gbs_algorithmic": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -593,8 +595,9 @@ def main():
         "config": {"workload": f"poiseuille_c2: 1024x513 body-force channel, g=1e-6, Kn={kn_t}, D2Q36 (order 4) "
                                "in 64 rows at each wall, D2Q9 core, Hermite interface, FP32 weight-shifted "
                                "populations", "nodes": nodes, "d2q36_nodes": counts[1], "d2q9_nodes": counts[0],
-                   "courant": 0.5,
-                   "courant_note": "per axis, fastest abscissa; stable because the channel stays bitwise x-uniform"},
+                   "courant": c["cfl"],
+                   "courant_note": "per axis, fastest abscissa; inside the unsplit update's stability limit for "
+                                   "flows varying in x and y (about 0.37 without collisions)"},
         "hbm_gbs_algorithmic": round(alg_bytes_step * args.steps / sec / 1e9, 1),
         "strip_rows": {"d2q9": strips[0], "d2q36": strips[1]},
         "work_shape": ",".join(str(v) for v in (*strips, *orders)),
@@ -695,7 +698,7 @@ def main():
         for nthr, ns in ((allc, 120), (1, 40)):
             oracle.set_threads(nthr)
             O = oracle.Lattice(c["nx"], c["ny"], kn=KN_TIMED, n_low=3, eq_low=2, n_high=6, eq_high=4, gx=c["gx"],
-                               dt=0.5 / float(np.max(x)))
+                               dt=c["cfl"] / float(np.max(x)))
             O.set_regions(*c["bands"])
             O.init_equilibrium()
             t0 = time.perf_counter()

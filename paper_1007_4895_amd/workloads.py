@@ -12,6 +12,8 @@ Workloads (all synthetic: the paper's cases are analytic channel flows):
   poiseuille_c2  body-force channel nx = 1024 x ny = 512, g = 1e-6,
                Kn in {0.01, 0.05, 0.1}, D2Q36 (4th order) in 64 rows at each
                wall, D2Q9 elsewhere, FP32, 10k steps; all-D2Q36 comparison.
+               Courant number 0.35 per axis for the fastest abscissa, inside
+               the unsplit update's limit for flows that vary in x and y.
   pressure_c3  pressure-driven channel nx = 4096 x ny = 256, rho_in/rho_out
                = 2, outlet Kn = 0.2 (relaxation time ~ 1/rho), bands per
                64-column tile from the non-equilibrium indicator every 500
@@ -32,7 +34,8 @@ Workloads (all synthetic: the paper's cases are analytic channel flows):
   thermal_couette  thermal Couette channel, the C2 geometry (nx = 1024 x
                ny = 512): walls moving -/+0.05 at temperatures 1.05 / 0.95,
                Kn = 0.01, thermal D2Q36 (4th order) in 64 rows at each wall,
-               thermal D2Q9 core, FP32, started at rest at T = 1.  Physics
+               thermal D2Q9 core, FP32, Courant 0.35, started at rest at
+               T = 1.  Physics
                check on an x-uniform channel nx = 4 x ny = 128, Kn = 0.05,
                16-row bands: steady conduction (walls at rest, T 1.02 /
                0.98) and shear heating (walls -/+0.1 at T = 1), M-D2Q9-36
@@ -41,8 +44,9 @@ Workloads (all synthetic: the paper's cases are analytic channel flows):
                [32, 512], Kn log-spaced in [0.01, 1], near-wall bands of
                8-64 rows (at most a third of the channel), velocity-set
                pairs D2Q9/D2Q16, D2Q9/D2Q36 and D2Q16/D2Q36 in turn,
-               Couette and Poiseuille alternating, FP32, stepped as one
-               batch in graph-captured segments of 5000 steps.
+               Couette and Poiseuille alternating, FP32, Courant 0.35,
+               stepped as one batch in graph-captured segments of 5000
+               steps.
 """
 from __future__ import annotations
 
@@ -89,7 +93,7 @@ COUETTE_C1 = dict(nx=4, ny=64, kn=0.1, n_low=D2Q9, n_high=D2Q16, eq_low=2, eq_hi
                   u_wall=((-0.05, 0.0), (0.05, 0.0)), bands=(8, 8), storage="f64", steps=20000)
 
 POISEUILLE_C2 = dict(nx=1024, ny=512, kn=0.05, kn_sweep=(0.01, 0.05, 0.1), n_low=D2Q9, n_high=D2Q36,
-                     eq_low=2, eq_high=4, gx=1e-6, bands=(64, 64), storage="f32", steps=10000)
+                     eq_low=2, eq_high=4, gx=1e-6, bands=(64, 64), cfl=0.35, storage="f32", steps=10000)
 
 PRESSURE_C3 = dict(nx=4096, ny=256, kn=0.2, n_low=D2Q9, n_high=D2Q36, eq_low=2, eq_high=4,
                    rho_in=2.0, rho_out=1.0, tile_w=64, theta=0.01, bmin=8, bmax=64, regrid=500,
@@ -101,7 +105,8 @@ OSC_COUETTE = dict(nx=8, ny=100, kn=0.0178, kn_sweep=(0.0178, 0.1, 0.3), u_osc=0
 KRAMERS = dict(nx=8, ny=400, kn=0.005, shear=1e-4, band=20, storage="f64")
 
 THERMAL_COUETTE = dict(nx=1024, ny=512, kn=0.01, n_low=D2Q9, n_high=D2Q36, eq_low=2, eq_high=4,
-                       u_wall=((-0.05, 0.0), (0.05, 0.0)), T_wall=(1.05, 0.95), bands=(64, 64), storage="f32",
+                       u_wall=((-0.05, 0.0), (0.05, 0.0)), T_wall=(1.05, 0.95), bands=(64, 64), cfl=0.35,
+                       storage="f32",
                        physics=dict(nx=4, ny=128, kn=0.05, bands=16, steps=80000, storage="f64",
                                     pairs=((3, 2, 6, 4), (4, 3, 6, 4)),
                                     cases={"conduction": dict(u_wall=((0.0, 0.0), (0.0, 0.0)), T_wall=(1.02, 0.98)),
@@ -109,7 +114,7 @@ THERMAL_COUETTE = dict(nx=1024, ny=512, kn=0.01, n_low=D2Q9, n_high=D2Q36, eq_lo
                                                                  T_wall=(1.0, 1.0))}))
 
 BATCH_C5 = dict(count=128, nx=8, ny_range=(32, 512), kn_range=(0.01, 1.0), band_range=(8, 64),
-                pairs=((3, 2, 4, 3), (3, 2, 6, 4), (4, 3, 6, 4)), u_wall=0.05, gx=1e-6, storage="f32",
+                pairs=((3, 2, 4, 3), (3, 2, 6, 4), (4, 3, 6, 4)), u_wall=0.05, gx=1e-6, cfl=0.35, storage="f32",
                 segment=5000, seed=51)
 
 
@@ -128,7 +133,7 @@ def batch_cases(c=BATCH_C5, count=None):
         nl, el, nh, eh = c["pairs"][k % len(c["pairs"])]
         couette = k % 2 == 0
         out.append(dict(nx=c["nx"], ny=ny, kn=float(kns[k]), n_low=nl, eq_low=el, n_high=nh, eq_high=eh,
-                        bands=(b, b), storage=c["storage"],
+                        bands=(b, b), storage=c["storage"], cfl=c["cfl"],
                         u_wall=((-c["u_wall"], 0.0), (c["u_wall"], 0.0)) if couette else ((0.0, 0.0), (0.0, 0.0)),
                         gx=0.0 if couette else c["gx"]))
     return out

@@ -176,7 +176,7 @@ def _c5(lb, count=None):
     L = []
     for c in cases:
         p = lb.make_params(c["nx"], c["ny"], kn=c["kn"], n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"],
-                           eq_high=c["eq_high"], storage=c["storage"], u_wall=c["u_wall"], gx=c["gx"])
+                           eq_high=c["eq_high"], storage=c["storage"], u_wall=c["u_wall"], gx=c["gx"], cfl=c["cfl"])
         x = lb.Lattice(p)
         x.set_regions(*c["bands"])
         x.init_equilibrium()

@@ -307,7 +307,7 @@ def test_thermal_couette_full_size_x_uniform(oracle, lb):
     c = W.THERMAL_COUETTE
     steps = 1000
     x, _ = oracle.gh_rule(6)
-    dt = 0.5 / float(np.max(x))
+    dt = c["cfl"] / float(np.max(x))
     kw = dict(n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"], eq_high=c["eq_high"], kn=c["kn"],
               u_wall=c["u_wall"], T_wall=c["T_wall"])
     G = lb.Lattice(lb.make_params(c["nx"], c["ny"], storage=c["storage"], dt=dt, thermal=True, **kw))

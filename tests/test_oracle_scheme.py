@@ -4,8 +4,9 @@ The checks are properties the method fixes: the minmod limiter equals the
 ratio form of Sec. 3.1, mirror symmetry, exact upwind shifts at Courant
 number 1, no new extrema (TVD), Lax-Wendroff where the limiter is inactive,
 exact mass/momentum bookkeeping on periodic lattices, x-uniform states that
-stay x-uniform bit for bit, zero normal mass flux at diffuse walls, and
-equilibrium fixed points.
+stay x-uniform bit for bit, zero normal mass flux at diffuse walls,
+equilibrium fixed points, and the Courant limit of the unsplit update for
+data varying in x and y.
 """
 import math
 
@@ -120,6 +121,29 @@ def test_unsplit_update_2d_courant_limit(oracle):
         amp[cfl] = np.nanmax(np.abs(f - w[:, None, None]) / w[:, None, None])
     assert amp[0.3] <= 0.1 + 1e-12
     assert not (amp[0.45] < 1.0)
+
+
+def test_benchmark_courant_number_damps_2d_perturbations(oracle):
+    # D2Q36 (order 4) with the relaxation time of the body-force channel at
+    # Kn 0.01 (tau0 = 0.01 x 512 = 5.12 = 0.08 x 64) on a 16 x 65 lattice,
+    # seeded density noise of 1e-6 varying in x and y: at the Courant
+    # number the benchmark channels use, the noise decays; at 0.5 (stable
+    # only for states that stay exactly x-uniform) it grows without bound
+    from paper_1007_4895_amd import workloads as W
+
+    nx, ny = 16, 64
+    x, _ = oracle.gh_rule(6)
+    noise = 1e-6 * W.rng(7).standard_normal((ny + 1, nx))
+    amp = {}
+    for cfl, steps in ((W.POISEUILLE_C2["cfl"], 800), (0.5, 400)):
+        L = _lattice(oracle, nx, ny, kn=0.08, n_low=6, n_high=6, eq_low=4, gx=1e-6, dt=cfl / float(np.max(x)))
+        L.init_equilibrium(rho=1.0 + noise)
+        L.step(steps)
+        r, _, _ = L.moments()
+        amp[cfl] = float(np.max(np.abs(r - r.mean(axis=1, keepdims=True))))
+    assert W.POISEUILLE_C2["cfl"] < 0.37
+    assert amp[W.POISEUILLE_C2["cfl"]] < 1e-9
+    assert not (amp[0.5] < 1e-3)
 
 
 @pytest.mark.parametrize("n", [3, 4, 6])
