@@ -76,6 +76,10 @@ def make(lb, W, kn, all_high, bands=None):
     return L
 
 
+# in the timed region, events around the dominant kernel of every 20th step
+TIMING_EVERY = 20
+
+
 def timed(L, steps, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -483,8 +487,9 @@ def main():
     ap.add_argument("--thermal-only", action="store_true",
                     help="run only the thermal Couette section (with --quick: its coupled run only, for "
                          "profiling; work shape from --shape, default 1,2,1,1)")
-    ap.add_argument("--profile-steps", type=int, default=2000,
-                    help="steps of the kernel-timing pass (the dominant kernel's roofline)")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="0: time the dominant kernel with events inside the timed region; N > 0: in a "
+                         "separate pass of N steps after it (profiler runs)")
     ap.add_argument("--shape", type=str, default="",
                     help="work shape of the coupled run as ROWS_LOW,ROWS_HIGH,ORDER_LOW,ORDER_HIGH "
                          "(skips its autotuner; reproduces a tuned run under a profiler)")
@@ -543,19 +548,30 @@ def main():
         Lc.autotune(100)
     strips, orders = Lc.work_shape()
     Lc.step(args.warmup)
+    nprof = args.profile_steps
+    if nprof <= 0:
+        # the roofline's kernel duration comes from HIP events around the
+        # dominant kernel's launches inside the timed region itself, on every
+        # TIMING_EVERY-th step (events on every launch add about 5 us of
+        # launch cost per step); an untimed pass first creates the lattice's
+        # event pool, so the timed region creates none
+        Lc.set_timing(True, every=TIMING_EVERY)
+        Lc.step(args.steps)
+        Lc.set_timing(True, every=TIMING_EVERY)
     sec = timed(Lc, args.steps, torch)
     cons = Lc.conservation()
     mlups = nodes * args.steps / sec / 1e6
     alg_bytes_step = 4 * 2 * (counts[0] * 9 + counts[1] * 36)
     print(f"coupled: {args.steps} steps in {sec:.4f} s, {mlups:.1f} MLUPS", flush=True)
 
-    # roofline of the dominant kernel (the D2Q36 update): HIP events around
-    # every launch on the lattice stream over a timed region
-    # (timing mode launches every kernel on the lattice stream, so the
-    # kernel's duration is its own, not shared with the concurrent set)
-    nprof = args.profile_steps
-    Lc.set_timing(True)
-    Lc.step(nprof)
+    # roofline of the dominant kernel (the merged update of both sets): HIP
+    # events around every launch on the lattice stream, over the timed
+    # region (or, with --profile-steps N, over a separate region of N steps
+    # for profiler runs); timing mode launches every kernel on the lattice
+    # stream, so the kernel's duration is its own
+    if nprof > 0:
+        Lc.set_timing(True)
+        Lc.step(nprof)
     ms_h, n_h, ms_all, n_all = Lc.kernel_times()
     Lc.set_timing(False)
     avg_ms = ms_h / max(n_h, 1)
@@ -586,7 +602,10 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "copy_same_bytes_gbs": round(copy_gbs, 1),
                 "kernel": "k_update_pair<F32, D2Q9 order 2 + D2Q36 order 4>", "bytes_per_launch": dom_bytes,
-                "avg_launch_ms": round(avg_ms, 5), "launches": n_h, "timing": "hipExtLaunchKernelGGL events"}
+                "avg_launch_ms": round(avg_ms, 5), "launches": n_h,
+                "timing": ("hipExtLaunchKernelGGL events on the dominant kernel of every "
+                           f"{TIMING_EVERY}th step of the timed region" if nprof <= 0 else
+                           f"hipExtLaunchKernelGGL events over {nprof} steps after the timed region")}
     out = {
         "metric": "coupled-LB MLUPS (D2Q9 core + D2Q36 near-wall bands) vs all-D2Q36",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

@@ -221,8 +221,10 @@ lb_status lb_change_regions(lb_lattice *L, const int32_t *band_lo, const int32_t
 lb_status lb_project(int32_t ns, int32_t eqs, int32_t nd, int32_t eqd, const double *f_src,
                      const double *closure, double *f_dst, int64_t n, void *hip_stream);
 
-/* Kernel timing: when enabled, every update-kernel launch records start and
- * stop HIP events (hipExtLaunchKernelGGL) on the lattice stream; lb_kernel_times returns, for the
+/* Kernel timing: enable = N >= 1 turns it on, and the update-kernel launches
+ * of every Nth step (step count divisible by N; N = 1: every step) record
+ * start and stop HIP events (hipExtLaunchKernelGGL) on the lattice stream;
+ * 0 turns it off, a negative value is LB_EINVAL.  lb_kernel_times returns, for the
  * dominant update kernel (the set that moves the most bytes per step) and
  * for all update kernels, the summed duration in ms and the launch count,
  * then clears them.  Waits. */

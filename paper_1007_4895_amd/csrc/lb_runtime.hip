@@ -321,6 +321,7 @@ struct lb_lattice {
     int order[2];        // item order per set: 0 = XCD slabs row-major, 1 = column-major
     double *d_stage, *d_mom, *d_part;
     bool timing;
+    int32_t timing_every = 1;   // in timing mode, events on every Nth step's update launches
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used;
     std::vector<int> ev_kind;   // per event pair: 1 = dominant update kernel, 0 = other update
@@ -590,6 +591,9 @@ lb_status one_step(lb_lattice *L) {
     a.cur = L->cur;
     a.seed = step_seed(L->step);
     const bool par = L->concurrent && !L->timing && L->nitems[0] && L->nitems[1] && L->p.iface == LB_IFACE_HERMITE;
+    // (timing mode records events around the update launches of every Nth
+    // step; the launches themselves are the same in every step)
+    const bool timed_now = L->timing && L->step % L->timing_every == 0;
     if (par && !L->side) {
         lb_status st = make_side_stream(L);
         if (st != LB_OK) return st;
@@ -618,7 +622,7 @@ lb_status one_step(lb_lattice *L) {
         const int sp = L->ks[0]->pair_split;
         const int nb_h = L->nitems[1] ? 8 * sa[1].chunk : 0, nb_l = 8 * ((sa[0].chunk + sp - 1) / sp);
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (L->timing) {
+        if (timed_now) {
             e0 = next_event(L);
             e1 = next_event(L);
             if (!e0 || !e1) return fail(LB_EDEVICE, "event creation failed");
@@ -635,7 +639,7 @@ lb_status one_step(lb_lattice *L) {
         a.items = L->d_items[s];
         a.nitems = L->nitems[s];
         a.chunk = (a.nitems + 7) / 8;
-        if (L->timing) {
+        if (timed_now) {
             hipEvent_t e0 = next_event(L), e1 = next_event(L);
             if (!e0 || !e1) return fail(LB_EDEVICE, "event creation failed");
             L->ev_kind.push_back(s);
@@ -995,6 +999,7 @@ lb_status lb_autotune(lb_lattice *L, int32_t steps, int32_t rows_out[2]) {
             double t = 1e300;
             for (int rep = 0; rep < 2; ++rep) {
                 L->timing = true;
+                L->timing_every = 1;
                 L->ev_used = 0;
                 L->ev_kind.clear();
                 for (int k = 0; k < steps; ++k)
@@ -1456,8 +1461,10 @@ lb_status lb_set_concurrency(lb_lattice *L, int32_t enable) {
 
 lb_status lb_set_timing(lb_lattice *L, int32_t enable) {
     if (!L) return fail(LB_EINVAL, "null lattice");
+    if (enable < 0) return fail(LB_EINVAL, "timing takes 0 (off) or a step interval >= 1");
     HIPCHK(hipStreamSynchronize(L->stream));
     L->timing = enable != 0;
+    L->timing_every = enable > 0 ? enable : 1;
     L->ev_used = 0;
     L->ev_kind.clear();
     return LB_OK;

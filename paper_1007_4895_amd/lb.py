@@ -331,8 +331,9 @@ class Lattice:
         return B
 
     # ---------------------------------------------------------------- timing
-    def set_timing(self, on=True):
-        _check(lib().lb_set_timing(self._h, 1 if on else 0))
+    def set_timing(self, on=True, every=1):
+        """Events around the update launches of every `every`-th step."""
+        _check(lib().lb_set_timing(self._h, int(every) if on else 0))
 
     def kernel_times(self):
         mh, ma = C.c_double(), C.c_double()

@@ -286,6 +286,34 @@ def test_strip_rows_invariance_and_determinism(lb):
             np.testing.assert_array_equal(x, y)
 
 
+def test_sampled_kernel_timing(lb):
+    # timing mode with an interval N records events around the update
+    # launches of the steps whose count is divisible by N only, and the
+    # populations do not depend on it
+    def make():
+        G = lb.Lattice(lb.make_params(200, 60, kn=0.1, n_low=3, n_high=6, eq_low=2, eq_high=4, storage="f32",
+                                      gx=1e-5, cfl=0.3))
+        G.set_regions(10, 12)
+        G.init_equilibrium()
+        G.step(4)
+        return G
+
+    A, B = make(), make()
+    A.set_timing(True, every=3)
+    A.step(10)                      # steps 4..13: 6, 9 and 12 are timed
+    ms_h, n_h, ms_all, n_all = A.kernel_times()
+    assert n_h == 3 and n_all == 3 and ms_h > 0
+    A.set_timing(True)
+    A.step(5)
+    assert A.kernel_times()[1] == 5
+    A.set_timing(False)
+    B.step(15)
+    np.testing.assert_array_equal(A.get_populations(0), B.get_populations(0))
+    np.testing.assert_array_equal(A.get_populations(1), B.get_populations(1))
+    with pytest.raises(lb.LBError):
+        A.set_timing(True, every=-2)
+
+
 def test_autotune_restores_state(lb):
     G = lb.Lattice(lb.make_params(256, 60, kn=0.1, n_low=3, n_high=6, eq_low=2, eq_high=4, storage="f32",
                                   gx=1e-5, u_wall=((0.01, 0.0), (-0.01, 0.0))))
