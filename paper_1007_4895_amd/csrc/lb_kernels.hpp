@@ -1703,6 +1703,15 @@ __device__ void closure_coeffs(const W &w, const ClosureNorm &cn, const double *
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
+// tanh of the inference layers: 1 - 2 / (exp(2|x|) + 1) with the
+// hardware exponential and reciprocal, sign restored (absolute error about
+// 1e-7, inside the 16 significant bits the next layer takes; for large |x|
+// the exponential overflows to infinity and the result is exactly 1)
+__device__ __forceinline__ float tanh_fast(float x) {
+    const float e = __expf(2.0f * fabsf(x));
+    return copysignf(1.0f - __fdividef(2.0f, e + 1.0f), x);
+}
+
 __device__ __forceinline__ void bf16_split(float v, short &hi, short &lo) {
     const uint16_t h = f_to_bf16(v);
     hi = short(h);
@@ -1743,7 +1752,7 @@ __device__ __forceinline__ void closure_mfma16(const uint16_t *w, const ClosureN
     for (int t = 0; t < 4; ++t) {
         const float b1 = bf16_to_f(w[MLP_OFF_B1 + 16 * t + r]);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) hs[4 * kq + v][16 * t + r] = tanhf(acc[t][v] + b1);
+        for (int v = 0; v < 4; ++v) hs[4 * kq + v][16 * t + r] = tanh_fast(acc[t][v] + b1);
     }
     __syncthreads();
     // layers 2 and 3: [16 x 64] x [64 x 64], then [16 x 64] x [64 x 16 (8 used)]
@@ -1780,7 +1789,7 @@ __device__ __forceinline__ void closure_mfma16(const uint16_t *w, const ClosureN
             for (int t = 0; t < 4; ++t) {
                 const float b2 = bf16_to_f(w[MLP_OFF_B2 + 16 * t + r]);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) hs[4 * kq + v][16 * t + r] = tanhf(acc[t][v] + b2);
+                for (int v = 0; v < 4; ++v) hs[4 * kq + v][16 * t + r] = tanh_fast(acc[t][v] + b2);
             }
             __syncthreads();
         } else if (r < 6) {
@@ -1797,6 +1806,17 @@ __device__ __forceinline__ void closure_mfma16(const uint16_t *w, const ClosureN
         }
     }
     __syncthreads();
+}
+
+// the network's bf16 weights copied to LDS by the block's threads in
+// 16-byte pieces (the layers then read their operands from LDS instead of
+// issuing two-byte global loads on the critical path); the caller's next
+// barrier publishes them
+static_assert(MLP_NPARAM * 2 % 16 == 0, "weights copy in 16-byte pieces");
+__device__ __forceinline__ void stage_closure_weights(const uint16_t *w, uint16_t *wl) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(w);
+    uint4 *dst = reinterpret_cast<uint4 *>(wl);
+    for (int k = threadIdx.x; k < MLP_NPARAM * 2 / 16; k += blockDim.x) dst[k] = src[k];
 }
 
 // standardised inputs and density of one D2Q9 node (absolute populations)
@@ -1826,9 +1846,11 @@ __global__ __launch_bounds__(64) void k_closure_infer(const StepArgs A) {
         __shared__ float hs[16][MLP_NH + 4];
         __shared__ float rs[16];
         __shared__ float c6[16][6];
+        __shared__ __attribute__((aligned(16))) uint16_t wl[MLP_NPARAM];
         const int lane = threadIdx.x;
         const int e0 = blockIdx.x * CLOSURE_NB;
         const int nn = min(CLOSURE_NB, A.nitems - e0);
+        stage_closure_weights(A.clw, wl);
         if (lane < 16) {
             if (lane < nn) {
                 const int e = e0 + lane;
@@ -1843,7 +1865,7 @@ __global__ __launch_bounds__(64) void k_closure_infer(const StepArgs A) {
             }
         }
         __syncthreads();
-        closure_mfma16(A.clw, A.cn, xs, hs, rs, c6);
+        closure_mfma16(wl, A.cn, xs, hs, rs, c6);
         for (int q = lane; q < 6 * nn; q += 64) A.clo[6 * e0 + q] = c6[q / 6][q % 6];
     }
 }
@@ -1862,10 +1884,12 @@ __global__ __launch_bounds__(64) void k_closure_flags(const NodeArgs A) {
         __shared__ float rs[16];
         __shared__ float c6[16][6];
         __shared__ float zf[16][2];
+        __shared__ __attribute__((aligned(16))) uint16_t wl[MLP_NPARAM];
         const int lane = threadIdx.x;
         const int64_t nodes = int64_t(A.g.nx) * A.g.nrow;
         const int64_t e0 = int64_t(blockIdx.x) * 16;
         const int nn = int(min(int64_t(16), nodes - e0));
+        stage_closure_weights(A.clw, wl);
         if (lane < 16) {
             if (lane < nn) {
                 const int64_t e = e0 + lane;
@@ -1886,7 +1910,7 @@ __global__ __launch_bounds__(64) void k_closure_flags(const NodeArgs A) {
             }
         }
         __syncthreads();
-        closure_mfma16(A.clw, A.cn, xs, hs, rs, c6, zf);
+        closure_mfma16(wl, A.cn, xs, hs, rs, c6, zf);
         if (lane < nn && zf[lane][1] > zf[lane][0]) A.out0[e0 + lane] = __builtin_huge_val();
     }
 }
