@@ -44,6 +44,10 @@ struct Inst {
     static void project_finish(const StepArgs &a, const int32_t *fin, int nfin, int nbp, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_project_finish<ST, S, O>), dim3(grid), dim3(128), 0, s, a, fin, nfin, nbp);
     }
+    static void project_closure(const StepArgs &a, const int32_t *fin, int nfin, int nbl, int nbd, int grid,
+                                hipStream_t s) {
+        hipLaunchKernelGGL((k_project_closure<ST, S, O>), dim3(grid), dim3(64), 0, s, a, fin, nfin, nbl, nbd);
+    }
     static void closure_infer(const StepArgs &a, int grid, hipStream_t s) {
         hipLaunchKernelGGL((k_closure_infer<ST, S, O>), dim3(grid), dim3(64), 0, s, a);
     }
@@ -134,6 +138,7 @@ struct Inst {
         k.paper_iface = &paper_iface;
         k.project = &project;
         k.closure_infer = &closure_infer;
+        k.project_closure = (S::N == 3 && O::N == 6 && !S::TH) ? &project_closure : nullptr;
         k.closure_samples = &closure_samples;
         k.closure_flags = &closure_flags;
         k.update_pair = update_split<S>() == 1 ? &update_pair : nullptr;

@@ -1598,6 +1598,8 @@ void k_batch_persistent(const PersistArgs P) {
 }
 
 // ------------------------------------------------------- learned closure
+// (the kernel that runs the closure inside the projection launch,
+// k_project_closure, follows the inference kernel below)
 // Network 10 -> 64 -> 64 -> 8 (tanh, tanh, linear); parameter layout
 // W1[64][10], b1[64], W2[64][64], b2[64], W3[8][64], b3[8].
 constexpr int MLP_NIN = 10, MLP_NH = 64, MLP_NOUT = 8;
@@ -1876,6 +1878,64 @@ __global__ __launch_bounds__(64) void k_closure_infer(const StepArgs A) {
 // threshold.  Inputs come from the node's D2Q9 populations, or from its
 // D2Q36 populations restricted to D2Q9 (Hermite projection) in the high
 // bands; one wave per 16 nodes, row-major.  self = low set, other = high.
+// A learned-closure step's inference, projection and finish pass in one
+// launch (one wave per block), instead of the inference launch before the
+// projection launch.  Blocks below nbl take 16 lifted nodes each: the
+// network's outputs stay in LDS and the same wave then projects those
+// nodes into the high set (6 target columns each), as k_project_halo does
+// with the outputs k_closure_infer stores; the next nbd blocks project the
+// high set's halo sources down (64 entries each), the remaining blocks
+// finish the nodes of `fin` (one thread per node and population).  The
+// three parts write disjoint entries and read only the updated copy.
+template <class ST, class LS, class HS>
+__global__ __launch_bounds__(64) void k_project_closure(const StepArgs A, const int32_t *fin, const int nfin,
+                                                        const int nbl, const int nbd) {
+    if constexpr (LS::N == 3 && HS::N == 6 && !LS::TH) {
+        const int b = blockIdx.x, lane = threadIdx.x;
+        if (b < nbl) {
+            __shared__ float xs[16][16];
+            __shared__ float hs[16][MLP_NH + 4];
+            __shared__ float rs[16];
+            __shared__ float c6[16][6];
+            __shared__ __attribute__((aligned(16))) uint16_t wl[MLP_NPARAM];
+            const int e0 = b * CLOSURE_NB;
+            const int nn = min(CLOSURE_NB, A.nitems - e0);
+            stage_closure_weights(A.clw, wl);
+            if (lane < 16) {
+                if (lane < nn) {
+                    const int e = e0 + lane;
+                    double f9[9];
+                    load_node_d<ST, LS>(A.self, A.cur ^ 1, A.items[2 * e], A.items[2 * e + 1], sh_of(A), f9);
+                    closure_inputs<LS>(A.cn, f9, A.ph.rho_ref, xs[lane], rs[lane]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) xs[lane][k] = 0.0f;
+                    rs[lane] = 0.0f;
+                }
+            }
+            __syncthreads();
+            closure_mfma16(wl, A.cn, xs, hs, rs, c6);   // ends with a barrier: c6 is complete
+            for (int k = lane; k < HS::N * nn; k += 64) {
+                const int n = k / HS::N, e = e0 + n;
+                project_entry<ST, LS, HS>(A, A.cur, true, A.items[2 * e], A.items[2 * e + 1], k % HS::N, c6[n]);
+            }
+            return;
+        }
+        if (b < nbl + nbd) {
+            const int64_t k = int64_t(b - nbl) * 64 + lane;
+            if (k >= int64_t(A.chunk) * LS::N) return;
+            const int e = int(k / LS::N) + A.nitems;
+            project_entry<ST, LS, HS>(A, A.cur, false, A.items[2 * e], A.items[2 * e + 1], int(k % LS::N), nullptr);
+            return;
+        }
+        constexpr int QM = finish_qmax<LS, HS>();
+        const int k = (b - nbl - nbd) * 64 + lane;
+        const int e = k / QM;
+        if (e >= nfin) return;
+        finish_pop<ST, LS, HS>(A, A.cur, fin[4 * e], fin[4 * e + 1], fin[4 * e + 2], k % QM);
+    }
+}
+
 template <class ST, class LS, class HS>
 __global__ __launch_bounds__(64) void k_closure_flags(const NodeArgs A) {
     if constexpr (LS::N == 3 && HS::N == 6 && !LS::TH) {

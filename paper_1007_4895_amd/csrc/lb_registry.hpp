@@ -18,6 +18,11 @@ using ProjFn = void (*)(const double *, const double *, double *, int64_t, hipSt
 using BatchFn = void (*)(const lbi::BatchArgs &, int grid, hipStream_t);
 // projection (nb_proj blocks) and finish pass over `fin` (nfin entries) in one launch
 using ProjFinFn = void (*)(const lbi::StepArgs &, const int32_t *fin, int nfin, int nb_proj, int grid, hipStream_t);
+// learned-closure steps: inference of the lifted nodes, the projection and
+// the finish pass in one launch (nb_lift closure blocks, nb_down projection
+// blocks, then the finish blocks up to grid)
+using ProjClFn = void (*)(const lbi::StepArgs &, const int32_t *fin, int nfin, int nb_lift, int nb_down, int grid,
+                          hipStream_t);
 // both sets' updates in one launch (self = low set, D2Q9 only): the blocks
 // of the high set come first
 using PairFn = void (*)(const lbi::StepArgs &low, const lbi::StepArgs &high, int nb_high, int nb_low, hipStream_t,
@@ -36,6 +41,7 @@ struct KernelSet {
     IfaceFn paper_iface;   // valid when `self` is the low set of the pair
     ProjFn project;        // FP64 projection self -> partner
     StepFn closure_infer;   // learned-closure inference of the lifted nodes (self = low set)
+    ProjClFn project_closure;   // closure + projection + finish in one launch; NULL but for D2Q9 / D2Q36
     NodeFn closure_samples; // training samples from an all-high run (self = high set)
     NodeFn closure_flags;   // the network's region flag into an indicator array (self = low set)
     PairFn update_pair;     // NULL unless the low set is D2Q9

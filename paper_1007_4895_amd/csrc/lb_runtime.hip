@@ -656,13 +656,26 @@ lb_status one_step(lb_lattice *L) {
         a.nitems = L->nproj[0];
         a.chunk = L->nproj[1];
         a.clo = nullptr;
+        // a learned-closure step runs the inference inside the projection
+        // launch (one launch fewer per step); the two-stream mode keeps the
+        // inference launch before the projection into the high set
+        const bool fused = L->closure_on && L->nproj[0] && !par && L->ks[0]->project_closure;
         if (L->closure_on && L->nproj[0]) {
-            a.clo = L->d_clo;
             a.clw = L->d_clw;
             a.cn = L->cn;
-            L->ks[0]->closure_infer(a, (L->nproj[0] + lbi::CLOSURE_NB - 1) / lbi::CLOSURE_NB, sl);
+            if (!fused) {
+                a.clo = L->d_clo;
+                L->ks[0]->closure_infer(a, (L->nproj[0] + lbi::CLOSURE_NB - 1) / lbi::CLOSURE_NB, sl);
+            }
         }
-        if (par) {
+        if (fused) {
+            const int nbl = (L->nproj[0] + lbi::CLOSURE_NB - 1) / lbi::CLOSURE_NB;
+            const int nbd = int((int64_t(L->nproj[1]) * L->n[0] + 63) / 64);
+            const int qm = std::max(L->Q[0], L->Q[1]);
+            const int nbf = int((int64_t(L->nfin) * qm + 63) / 64);
+            L->ks[0]->project_closure(a, L->d_fin, L->nfin, nbl, nbd, nbl + nbd + nbf, L->stream);
+            fin_done = true;
+        } else if (par) {
             // low -> high on the low set's stream, high -> low on the other
             StepArgs up = a, down = a;
             up.chunk = 0;

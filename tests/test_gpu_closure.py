@@ -220,6 +220,36 @@ def test_step_with_learned_closure(oracle, lb, mlp):
     assert d > 1e-7, d
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("channel", ["pressure", "periodic"])
+def test_closure_in_the_projection_launch_bit_identical(oracle, lb, mlp, storage, channel):
+    # a learned-closure step runs the inference inside the projection launch
+    # (with the pressure columns' finish pass when the lattice has one); the
+    # two-stream mode keeps the inference launch before the projection: the
+    # same populations, bit for bit
+    from paper_1007_4895_amd import closure
+    nx, ny, kn = 130, 40, 0.2
+    p, _, _, _ = _net(mlp, 8, 1)
+    norm = _trial_norm()
+    out = []
+    for two_streams in (False, True):
+        if channel == "pressure":
+            G = closure.channel(nx, ny, kn, storage=storage, all_high=False, bands=(6, 8))
+        else:
+            G = lb.Lattice(lb.make_params(nx, ny, kn=kn, n_low=3, eq_low=2, n_high=6, eq_high=4, storage=storage,
+                                          gx=1e-4, u_wall=((-0.02, 0.0), (0.02, 0.0)), cfl=0.3))
+            G.set_regions(7, 5)
+            rho, ux, uy = W.smooth_fields(nx, ny + 1, seed=91)
+            G.init_equilibrium(rho, ux, uy)
+        G.set_closure(_dev(p), norm)
+        if two_streams:
+            G.set_concurrency(True)
+        G.step(30)
+        out.append((G.get_populations(0), G.get_populations(1)))
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_region_change_with_learned_closure(oracle, lb, mlp):
     # nodes switched from D2Q9 to D2Q36 by a region change, and the halo
     # rebuilt after it, are lifted with the network; the oracle converts
