@@ -242,6 +242,32 @@ def test_poiseuille_c2_full_width_x_uniform(oracle, lb):
     assert rel_u(uxg[:, :4], uyg[:, :4], uxo, uyo) < 1e-5
 
 
+def test_poiseuille_c2_wide_4096_x_uniform(oracle, lb):
+    # the benchmark's 4096-column variant of the channel (4096 x 513, whose
+    # populations exceed the Infinity Cache), in the work shape its autotuner
+    # picks: bit-for-bit x-uniform, so every column is checked against the
+    # oracle run at nx = 4
+    c = W.POISEUILLE_C2
+    steps = 1000
+    x, _ = oracle.gh_rule(6)
+    dt = c["cfl"] / float(np.max(x))
+    kw = dict(n_low=c["n_low"], eq_low=c["eq_low"], n_high=c["n_high"], eq_high=c["eq_high"], kn=0.01,
+              gx=c["gx"])
+    G = lb.Lattice(lb.make_params(4 * c["nx"], c["ny"], storage=c["storage"], dt=dt, **kw))
+    G.set_regions(*c["bands"])
+    G.set_work_shape((7, 6), (1, 1))
+    G.init_equilibrium()
+    G.step(steps)
+    r_g, uxg, uyg = G.moments()
+    assert np.all(uxg == uxg[:, :1]) and np.all(r_g == r_g[:, :1])
+    O = oracle.Lattice(4, c["ny"], dt=dt, **kw)
+    O.set_regions(*c["bands"])
+    O.init_equilibrium()
+    O.step(steps)
+    r_o, uxo, uyo = O.moments()
+    assert rel_u(uxg[:, :4], uyg[:, :4], uxo, uyo) < 1e-5
+
+
 def test_poiseuille_c2_damps_2d_perturbations(lb):
     # the benchmark workload at full size, in the benchmark's work shape and
     # at its Courant number, started from seeded density noise of 1e-6 that
